@@ -1,0 +1,231 @@
+/*
+ * fgs.h -- C ABI of libfgs: RGB-D foreground segmentation (GMM and PBAS
+ * background models) on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes, for every pixel of every frame, the classify-and-
+ * update step of the two RGB-D background models of Janus, Kryjak and Gorgon,
+ * "Foreground object segmentation in RGB-D data implemented on GPU":
+ *   - FGS_GMM:  a colour Gaussian mixture and a depth Gaussian mixture per
+ *               pixel, combined into one decision (Sec. 3.1);
+ *   - FGS_PBAS: a Pixel-Based Adaptive Segmenter whose samples carry RGB and
+ *               depth, each component segmented and updated on its own
+ *               (Sec. 3.2).
+ * The host owns acquisition and allocates the model on the device; frames go
+ * in, a binary mask comes out (Sec. 4.2).  Everything per pixel runs in the
+ * library's own HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: every function returns fgs_status; FGS_OK is 0.  Nothing aborts
+ *    and nothing throws across this boundary.  fgs_last_error() returns a
+ *    thread-local description of the last failure on the calling thread.
+ *  - Images: RGB is interleaved 8-bit R,G,B; depth is uint16 millimetres with
+ *    0 meaning "no depth".  Rows are addressed with a byte stride >= the
+ *    packed row size.  Masks are uint8, 0 = background, 255 = foreground.
+ *  - Memory: fgs_mem tells whether a caller pointer is host or device memory.
+ *    The caller owns every buffer it passes; the library owns the model.
+ *    Device pointers are read/written in the model's stream order.
+ *  - Streams: a model runs on one HIP stream (hipStream_t passed as void*),
+ *    either the caller's or, when NULL is passed, one the library creates at
+ *    default priority.  A model is not thread-safe; distinct models are.
+ *  - Device errors poison the model: later calls on it return FGS_ERR_DEVICE
+ *    until fgs_destroy.
+ */
+#ifndef FGS_H
+#define FGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGS_ABI_VERSION 1
+
+typedef enum fgs_status {
+    FGS_OK = 0,
+    FGS_ERR_INVALID_ARG = 1,   /* bad pointer, size, stride, params or struct_size */
+    FGS_ERR_OUT_OF_MEMORY = 2, /* device or pinned host allocation failed */
+    FGS_ERR_DEVICE = 3,        /* a HIP call failed; the model is poisoned */
+    FGS_ERR_BAD_STATE = 4,     /* call not valid in the model's current state */
+    FGS_ERR_BUSY = 5,          /* resource temporarily unavailable */
+    FGS_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+} fgs_status;
+
+typedef enum fgs_algo { FGS_GMM = 1, FGS_PBAS = 2 } fgs_algo;
+
+typedef enum fgs_mem { FGS_MEM_HOST = 0, FGS_MEM_DEVICE = 1 } fgs_mem;
+
+typedef struct fgs_model fgs_model; /* opaque, owned by the library */
+
+/*
+ * GMM constants (Sec. 3.1).  Each pixel holds Kc colour Gaussians over (R,G,B)
+ * and Kd depth Gaussians over the 8-bit depth code, each Gaussian a weight w,
+ * a mean and one isotropic variance v.  Per frame, on the ranked pre-update
+ * mixtures: q_k = |X - mu_k|^2 / v_k; the background set is the leading
+ * Gaussians whose weights first sum past T_bg; delta_m = min q_k over it;
+ * foreground iff Z = (delta_c - lambda^2) + w_depth*(delta_d - lambda^2) >= 0,
+ * the depth term present only where depth > 0.  Update (Stauffer-Grimson):
+ * first Gaussian with q < lambda^2 matches, w <- (1-alpha)w (+alpha if matched),
+ * matched mean/variance move with rate alpha, v >= v_min; no match replaces the
+ * last Gaussian by (w_init, X, v_init); weights renormalised; ranked by
+ * w/sqrt(v), stable, descending.  The depth model is updated only where
+ * depth > 0.  Supported (Kc,Kd): (k,k) for k = 1..7, and (7,3).
+ */
+typedef struct fgs_gmm_params {
+    uint32_t struct_size; /* = sizeof(fgs_gmm_params) */
+    int32_t Kc, Kd;
+    float alpha;          /* learning rate (also the mean/variance rate) */
+    float lambda;         /* match threshold in standard deviations */
+    float T_bg;           /* background weight fraction */
+    float w_init;         /* weight of a replacement Gaussian */
+    float v_init_c, v_min_c; /* colour variance: new Gaussian, floor */
+    float v_init_d, v_min_d; /* depth variance: new Gaussian, floor */
+    float w_depth;        /* weight of the depth term in Z */
+    int32_t depth_max_mm; /* depth full scale: code = floor((255*D + M/2)/M), >= 1 */
+} fgs_gmm_params;
+
+/*
+ * PBAS constants (Sec. 3.2).  Per pixel: N samples (32-bit words, bytes R, G,
+ * B, depth code; depth code 0 = none recorded), and per channel j in
+ * {R,G,B,D} a decision threshold R_j, an update rate T_j, the history D_j of N
+ * minimal distances and its sum S_j.  The first N frames fill the samples.
+ * Then per active channel (depth only where depth > 0): foreground iff fewer
+ * than min_matches samples lie within R_j; a background channel replaces one
+ * random sample (and its D slot) with probability 1/T_j and writes a random
+ * 8-neighbour's own value into a random sample of that neighbour with
+ * probability 1/T_j; R_j and T_j then adapt to d_bar = S_j/N within
+ * [R_lower_j, inf) and [T_lower, T_upper].  Random words come from
+ * Philox4x32-10 keyed by `seed` with counter (y*W + x, frame, call, 0).
+ * Supported N: 2..64.
+ */
+typedef struct fgs_pbas_params {
+    uint32_t struct_size; /* = sizeof(fgs_pbas_params) */
+    int32_t N;
+    int32_t min_matches;
+    float R_incdec, R_scale;
+    float T_inc, T_dec, T_lower, T_upper;
+    float R_lower[4];     /* per channel R, G, B, depth */
+    int32_t depth_max_mm;
+    int32_t reserved0;
+    uint64_t seed;
+} fgs_pbas_params;
+
+/* ABI version of the loaded library (FGS_ABI_VERSION it was built with). */
+int32_t fgs_abi_version(void);
+
+/* Static English name of a status code.  Never NULL. */
+const char* fgs_status_str(fgs_status s);
+
+/* Thread-local text of the last failure on this thread ("" if none).  The
+ * pointer stays valid until the next fgs_* call on this thread. */
+const char* fgs_last_error(void);
+
+/* Fill *p with the default constants (the readings of Sec. 3.1 used by this
+ * library: Kc = Kd = 3, alpha 0.01, lambda 2.5, T_bg 0.7, w_init 0.05,
+ * v_init_c 675, v_min_c 12, v_init_d 25, v_min_d 1, w_depth 1, 10 m full scale).
+ * INVALID_ARG if p is NULL. */
+fgs_status fgs_gmm_params_default(fgs_gmm_params* p);
+
+/* Fill *p with the default PBAS constants (Sec. 3.2: N = 20; the rest from the
+ * base method: min_matches 2, R_incdec 0.05, R_scale 5, T_inc 1, T_dec 0.05,
+ * T in [2, 200], R_lower 18,18,18 and 4 for depth, 10 m full scale).
+ * INVALID_ARG if p is NULL. */
+fgs_status fgs_pbas_params_default(fgs_pbas_params* p);
+
+/*
+ * Create a model of `algo` for H x W frames (Sec. 4.2: the host allocates the
+ * background model in device memory).  `params` points to fgs_gmm_params or
+ * fgs_pbas_params matching `algo` (NULL = defaults).  `hip_stream` is the
+ * hipStream_t to run on, or NULL for a library-owned stream.  On success *out
+ * receives the model; its state is the fresh model (GMM: w = 0, mu = 0,
+ * v = v_init; PBAS: empty samples, R = R_lower, T = T_lower, D = S = 0).
+ * Errors: INVALID_ARG (H or W < 1, H*W > 2^28, bad params), OUT_OF_MEMORY,
+ * DEVICE.  Uses the current HIP device.
+ */
+fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params,
+                      void* hip_stream, fgs_model** out);
+
+/* Wait for the model's queued work, then free it.  NULL is accepted. */
+fgs_status fgs_destroy(fgs_model* m);
+
+/*
+ * Run one classify-and-update step on the next frame (Sec. 3.1 / 3.2, one
+ * launch per frame).  rgb: H rows of 3*W bytes at rgb_stride bytes apart;
+ * depth: H rows of W uint16 at depth_stride bytes apart (both >= packed row
+ * size).  where = FGS_MEM_HOST: the frame is copied to pinned staging and sent
+ * to the device before return (the host buffers may be reused at once);
+ * FGS_MEM_DEVICE: the kernel reads the device buffers in stream order, and the
+ * caller must not overwrite them before the step has run (fgs_sync or a later
+ * stream event).  Asynchronous otherwise: the mask is ready in stream order.
+ * Errors: INVALID_ARG, DEVICE.
+ */
+fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
+                          const uint16_t* depth, int64_t depth_stride, fgs_mem where);
+
+/*
+ * Copy the mask of the most recent frame into `mask` (H rows of W bytes,
+ * `stride` bytes apart).  FGS_MEM_HOST waits for the frame to finish;
+ * FGS_MEM_DEVICE enqueues a device copy on the model's stream.
+ * BAD_STATE before the first push.
+ */
+fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem where);
+
+/* Borrow the device pointer of the model's internal H*W mask buffer (valid
+ * until fgs_destroy; rewritten by every push, in stream order). */
+fgs_status fgs_mask_device_ptr(fgs_model* m, const uint8_t** out);
+
+/*
+ * Model state, serialised in a fixed layout (little-endian):
+ *   header (64 bytes): uint32 magic 0x53534746 ("FGSS"), uint32 version (1),
+ *     uint32 algo, int32 H, int32 W, int32 A, int32 B, int32 reserved,
+ *     int64 frames pushed, uint64 seed (PBAS, else 0), 16 bytes reserved.
+ *     A,B = Kc,Kd (GMM) or N,0 (PBAS).
+ *   GMM payload (float32 planes of H*W, row-major), in order:
+ *     w_c[Kc], mu_c[Kc][3] (R,G,B), v_c[Kc], w_d[Kd], mu_d[Kd], v_d[Kd]
+ *     (each model's Gaussians in rank order).
+ *   PBAS payload: samples[N] uint32 planes (bytes R,G,B,depth code),
+ *     dhist[N] uint32 planes (bytes D_R, D_G, D_B, D_D), R[4] float32 planes,
+ *     T[4] float32 planes, S[4] uint16 planes.
+ * fgs_state_size gives the byte count.  fgs_copy_state first applies any
+ * deferred PBAS neighbour writes (so the state is the logical model after the
+ * last frame), then copies; FGS_MEM_HOST waits for completion.  fgs_set_state
+ * replaces the model (including the frame counter, which keys the PBAS random
+ * stream) from such a blob for the same algo/H/W/A/B.
+ * Errors: INVALID_ARG (size or header mismatch), DEVICE.
+ */
+fgs_status fgs_state_size(const fgs_model* m, size_t* bytes);
+fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where);
+fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem where);
+
+/* Number of frames pushed so far (the next frame's index). */
+fgs_status fgs_frame_index(const fgs_model* m, int64_t* t);
+
+/* Block until all work queued on the model's stream has finished. */
+fgs_status fgs_sync(fgs_model* m);
+
+/* The hipStream_t (as void*) the model runs on. */
+fgs_status fgs_stream(const fgs_model* m, void** hip_stream);
+
+/* Device bytes the model holds (state, scratch planes, mask, input staging). */
+fgs_status fgs_device_bytes(const fgs_model* m, size_t* bytes);
+
+/*
+ * Diagnostics.
+ * fgs_philox4x32_10: for i < n, out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3],
+ *   key = (seed low 32 bits, seed high 32 bits)) (Salmon et al., SC'11) -- the
+ *   generator PBAS draws from.  ctr and out are device arrays of 4n uint32;
+ *   runs on hip_stream (NULL = default stream) and returns after enqueueing.
+ * fgs_copy_probe: a plain streaming device copy of `bytes` (multiple of 16,
+ *   both pointers 16-byte aligned) used to calibrate achievable HBM bandwidth.
+ */
+fgs_status fgs_philox4x32_10(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
+                             void* hip_stream);
+fgs_status fgs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGS_H */

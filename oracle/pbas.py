@@ -1,0 +1,208 @@
+"""RGB-D Pixel-Based Adaptive Segmenter: one classify-and-update step per frame.
+
+Oracle (test infrastructure only).  Plain numpy, vectorised over pixels, one
+loop over the N samples, the steps taken in the order of the method below.
+
+What the paper fixes (Sec. 3.2) and what is read in
+------------------------------------------------------
+* PBAS (Hofmann et al. 2012, cited, not restated) keeps per pixel a buffer of
+  N recent samples plus a second part, which the paper does not name; from the
+  base method that is the adaptive decision threshold R, the adaptive update
+  rate T and the history D of minimal decision distances.
+* In the RGB-D variant one sample holds the RGB value and the depth value, and
+  each component is segmented and updated on its own; depth takes part only
+  where the sensor depth is > 0 (Sec. 3.2).  N = 20 in the authors' system.
+  Samples are stored as 32-bit words, 8 bits per colour component and depth
+  (Sec. 4.2), depth coded by ``oracle.depth.depth_q8``.
+* Reading: four independent per-channel PBAS instances j in {R, G, B, D}; the
+  pixel is foreground when any active channel is.  A depth byte of 0 in a
+  sample means "no depth was recorded there": it never matches and is left out
+  of d_min.
+
+Per frame t and pixel x, for every active channel j (depth only if D(x) > 0):
+
+  init       for t < N, sample slot t takes I(x, t); the mask is 0 and R, T,
+             D, S stay at their initial values (R_lower, T_lower, 0, 0)
+  classify   dist_k = |I_j - B_k,j|;  cnt = #{k : dist_k < R_j};
+             d_min = min_k dist_k (255 if no sample);  F_j = cnt < #min
+  draws      two Philox4x32-10 blocks per pixel and frame, counter
+             (y*W + x, t, c, 0) for c = 0, 1, key = the 64-bit seed; word j of
+             block c serves channel j.  From a word w: u = (w >> 16) / 2^16.
+  self       if not F_j and u(w0_j) * T_j < 1 (T_j before this frame's update):
+             k = ((w0_j & 0xFFFF) * N) >> 16;  B_k,j = I_j;
+             S_j = S_j - D_k,j + d_min;  D_k,j = d_min
+  neighbour  if not F_j and u(w1_j) * T_j < 1: the 8-neighbour y in direction
+             (w1_j >> 13) & 7 (order: (-1,-1) (0,-1) (1,-1) (-1,0) (1,0)
+             (-1,1) (0,1) (1,1) as (dx, dy)) gets slot
+             k' = ((w1_j & 0x1FFF) * N) >> 13 of channel j set to y's own value
+             I_j(y, t); skipped if y is outside the image, and for depth unless
+             D(y) > 0
+  R          d_bar = S_j / N;  R_j = R_j * (1 - R_inc/dec) if R_j > d_bar * R_scale
+             else R_j * (1 + R_inc/dec);  R_j = max(R_j, R_lower,j)
+  T          T_j = T_j + T_inc / d_bar if F_j else T_j - T_dec / d_bar
+             (IEEE: d_bar = 0 gives +-inf), clamped to [T_lower, T_upper]
+
+Every write into pixel y's samples during frame t carries y's own value at t,
+and D, S are touched only by the pixel itself, so the result does not depend
+on the order in which pixels are processed.  Classification of every pixel at
+frame t sees the model as left by frame t-1.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from .depth import DEPTH_MAX_MM, depth_q8
+from .philox import philox4x32_10, seed_key
+
+# 8-neighbourhood, indexed by the 3-bit direction field.
+NB_DX = np.array([-1, 0, 1, -1, 1, -1, 0, 1], np.int64)
+NB_DY = np.array([-1, -1, -1, 0, 0, 1, 1, 1], np.int64)
+
+PBAS_DEFAULT_SEED = 0x2002_0025_0
+
+
+@dataclass
+class PbasParams:
+    """Constants.  N from Sec. 3.2; the rest are the base method's published defaults,
+    except the depth channel's R_lower (4 codes, about 16 cm), a reading."""
+    N: int = 20
+    min_matches: int = 2
+    R_incdec: float = 0.05
+    R_scale: float = 5.0
+    T_inc: float = 1.0
+    T_dec: float = 0.05
+    T_lower: float = 2.0
+    T_upper: float = 200.0
+    R_lower: tuple = (18.0, 18.0, 18.0, 4.0)
+    depth_max_mm: int = DEPTH_MAX_MM
+    seed: int = PBAS_DEFAULT_SEED
+
+
+def pbas_draws(H: int, W: int, t: int, seed: int):
+    """Philox words for frame t: (w0, w1), each uint32 [H, W, 4] (word j -> channel j)."""
+    k0, k1 = seed_key(seed)
+    pix = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    out = []
+    for c in (0, 1):
+        x = philox4x32_10(pix, np.uint64(t), np.uint64(c), np.uint64(0), k0, k1)
+        out.append(np.stack(x, axis=-1))
+    return out[0], out[1]
+
+
+class PbasRef:
+    """The RGB-D PBAS over an H x W image.  ``step(rgb, depth) -> mask``."""
+
+    def __init__(self, H: int, W: int, params: PbasParams | None = None):
+        self.p = params or PbasParams()
+        self.H, self.W = H, W
+        N = self.p.N
+        self.samples = np.zeros((N, H, W, 4), np.uint8)
+        self.D = np.zeros((N, H, W, 4), np.uint8)
+        self.S = np.zeros((H, W, 4), np.int64)
+        self.R = np.broadcast_to(np.array(self.p.R_lower, np.float32), (H, W, 4)).copy()
+        self.T = np.full((H, W, 4), np.float32(self.p.T_lower), np.float32)
+        self.t = 0
+        self.last_F = None
+        self.last_draws = None
+
+    def frame_value(self, rgb, depth) -> np.ndarray:
+        """I(x, t): RGB bytes plus the depth code (0 where depth is invalid)."""
+        I = np.empty((self.H, self.W, 4), np.uint8)
+        I[..., :3] = rgb
+        I[..., 3] = depth_q8(depth, self.p.depth_max_mm)
+        return I
+
+    def step(self, rgb: np.ndarray, depth: np.ndarray) -> np.ndarray:
+        p = self.p
+        H, W, N = self.H, self.W, p.N
+        I = self.frame_value(rgb, depth)
+        valid = np.asarray(depth) > 0
+        active = np.ones((H, W, 4), np.bool_)
+        active[..., 3] = valid
+
+        if self.t < N:                      # initialisation: fill slot t
+            self.samples[self.t] = I
+            self.t += 1
+            self.last_F = np.zeros((H, W, 4), np.bool_)
+            return np.zeros((H, W), np.uint8)
+
+        # Segmentation against the model left by frame t-1.
+        Ii = I.astype(np.int16)
+        cnt = np.zeros((H, W, 4), np.int64)
+        dmin = np.full((H, W, 4), 255, np.int16)
+        for k in range(N):
+            s = self.samples[k]
+            dist = np.abs(s.astype(np.int16) - Ii)
+            filled = np.ones((H, W, 4), np.bool_)
+            filled[..., 3] = s[..., 3] != 0
+            cnt += filled & (dist < self.R)
+            dmin = np.where(filled, np.minimum(dmin, dist), dmin)
+        F = active & (cnt < p.min_matches)
+        mask = np.where(F.any(axis=-1), 255, 0).astype(np.uint8)
+        bg = active & ~F
+
+        w0, w1 = pbas_draws(H, W, self.t, p.seed)
+        self.last_draws = (w0, w1)
+        scale = np.float32(1.0 / 65536.0)
+        T_prev = self.T
+
+        # Self-update: a random sample and its d_min slot, with probability 1/T.
+        u0 = (w0 >> np.uint32(16)).astype(np.float32) * scale
+        upd = bg & (u0 * T_prev < np.float32(1.0))
+        kself = (((w0 & np.uint32(0xFFFF)).astype(np.uint64) * np.uint64(N)) >> np.uint64(16)).astype(np.int64)
+        ys, xs, js = np.nonzero(upd)
+        ks = kself[ys, xs, js]
+        self.samples[ks, ys, xs, js] = I[ys, xs, js]
+        old = self.D[ks, ys, xs, js].astype(np.int64)
+        dm = dmin[ys, xs, js].astype(np.int64)
+        self.S[ys, xs, js] += dm - old
+        self.D[ks, ys, xs, js] = dm.astype(np.uint8)
+
+        # Neighbour update: a random neighbour's random sample takes the neighbour's own value.
+        u1 = (w1 >> np.uint32(16)).astype(np.float32) * scale
+        nb = bg & (u1 * T_prev < np.float32(1.0))
+        direc = ((w1 >> np.uint32(13)) & np.uint32(7)).astype(np.int64)
+        knb = (((w1 & np.uint32(0x1FFF)).astype(np.uint64) * np.uint64(N)) >> np.uint64(13)).astype(np.int64)
+        ys, xs, js = np.nonzero(nb)
+        d = direc[ys, xs, js]
+        ny, nx = ys + NB_DY[d], xs + NB_DX[d]
+        ok = (ny >= 0) & (ny < H) & (nx >= 0) & (nx < W)
+        ys, xs, js, ny, nx = ys[ok], xs[ok], js[ok], ny[ok], nx[ok]
+        ok = (js < 3) | valid[ny, nx]
+        ys, xs, js, ny, nx = ys[ok], xs[ok], js[ok], ny[ok], nx[ok]
+        self.samples[knb[ys, xs, js], ny, nx, js] = I[ny, nx, js]
+
+        # Decision threshold and update rate.
+        f = np.float32
+        with np.errstate(divide="ignore"):
+            dbar = self.S.astype(f) / f(N)
+            R_new = np.where(self.R > dbar * f(p.R_scale),
+                             self.R * (f(1) - f(p.R_incdec)), self.R * (f(1) + f(p.R_incdec)))
+            R_new = np.maximum(R_new, np.array(p.R_lower, f))
+            T_new = np.where(F, self.T + f(p.T_inc) / dbar, self.T - f(p.T_dec) / dbar)
+        T_new = np.minimum(np.maximum(T_new, f(p.T_lower)), f(p.T_upper))
+        self.R = np.where(active, R_new, self.R).astype(f)
+        self.T = np.where(active, T_new, self.T).astype(f)
+        self.last_F = F
+        self.last_self = upd
+        self.last_nb = nb
+        self.t += 1
+        return mask
+
+    # State in the library's canonical plane order (see include/fgs.h).
+    def state_planes(self) -> dict:
+        return dict(samples=np.ascontiguousarray(self.samples).view(np.uint32)[..., 0],
+                    dhist=np.ascontiguousarray(self.D).view(np.uint32)[..., 0],
+                    R=np.moveaxis(self.R, -1, 0).copy(), T=np.moveaxis(self.T, -1, 0).copy(),
+                    S=np.moveaxis(self.S, -1, 0).astype(np.uint16), t=self.t)
+
+    def set_state_planes(self, st: dict) -> None:
+        N, H, W = self.p.N, self.H, self.W
+        self.samples = np.ascontiguousarray(st["samples"], np.uint32).view(np.uint8).reshape(N, H, W, 4).copy()
+        self.D = np.ascontiguousarray(st["dhist"], np.uint32).view(np.uint8).reshape(N, H, W, 4).copy()
+        self.R = np.moveaxis(np.asarray(st["R"], np.float32), 0, -1).copy()
+        self.T = np.moveaxis(np.asarray(st["T"], np.float32), 0, -1).copy()
+        self.S = np.moveaxis(np.asarray(st["S"]), 0, -1).astype(np.int64)
+        self.t = int(st["t"])

@@ -1,0 +1,350 @@
+"""Pins for the GMM oracle (Sec. 3.1 and the Stauffer-Grimson mixture it adapts).
+
+Each test checks the oracle against something other than itself: closed forms of the
+recursion under a constant input, hand-derived cases (tests/golden), the textbook
+colour-only Stauffer-Grimson rule that the RGB-D decision must reduce to, and
+invariants of the model."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.gmm import GmmParams, GmmRef
+from oracle.depth import depth_q8
+from synth import Scene, preset
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "gmm_hand_cases.json")
+
+
+def _params(**kw):
+    return GmmParams(**kw)
+
+
+def _single(params, wc, muc, vc, wd=None, mud=None, vd=None, dtype=np.float32):
+    """A 1x1 model with a given state."""
+    g = GmmRef(1, 1, params, dtype=dtype)
+    Kc, Kd = params.Kc, params.Kd
+    st = dict(w_c=np.array(wc, dtype).reshape(Kc, 1, 1),
+              mu_c=np.array(muc, dtype).reshape(Kc, 3, 1, 1),
+              v_c=np.array(vc, dtype).reshape(Kc, 1, 1),
+              w_d=np.array(wd if wd is not None else [0] * Kd, dtype).reshape(Kd, 1, 1),
+              mu_d=np.array(mud if mud is not None else [0] * Kd, dtype).reshape(Kd, 1, 1),
+              v_d=np.array(vd if vd is not None else [params.v_init_d] * Kd, dtype).reshape(Kd, 1, 1),
+              t=5)
+    g.set_state_planes(st)
+    return g
+
+
+def _frame(rgb, D):
+    return (np.array(rgb, np.uint8).reshape(1, 1, 3), np.array([[D]], np.uint16))
+
+
+def test_hand_replacement_and_match_cases():
+    gold = json.load(open(GOLD))
+    p = _params(**gold["params"])
+    for case in gold["replacement_cases"]:
+        g = _single(p, case["w"], case["mu"], case["v"])
+        m = g.step(*_frame(case["X"], 0))
+        st = g.state_planes()
+        np.testing.assert_allclose(st["w_c"][:, 0, 0], case["expect_w"], rtol=2e-6, atol=1e-7,
+                                   err_msg=case["name"])
+        np.testing.assert_allclose(st["mu_c"][:, :, 0, 0], case["expect_mu"], rtol=2e-6,
+                                   err_msg=case["name"])
+        np.testing.assert_allclose(st["v_c"][:, 0, 0], case["expect_v"], rtol=2e-6, err_msg=case["name"])
+        assert np.isclose(g.last_Z[0, 0], case["expect_Z"], rtol=1e-6), case["name"]
+        assert m[0, 0] == case["expect_mask"], case["name"]
+
+
+def test_hand_decision_cases():
+    gold = json.load(open(GOLD))
+    dc = gold["decision_cases"][0]
+    for c in dc["cases"]:
+        p = _params(**{**gold["params"], "w_depth": c["w_depth"]})
+        g = _single(p, [1, 0, 0], [[100, 100, 100], [0, 0, 0], [0, 0, 0]], [3, 675, 675],
+                    wd=[1, 0, 0], mud=[40, 0, 0], vd=[1, 25, 25])
+        m = g.step(*_frame(dc["rgb"], c["D"]))
+        assert g.last_Z[0, 0] == np.float32(c["Z"]), c
+        assert m[0, 0] == c["mask"], c
+
+
+def test_constant_frame_from_fresh_model_closed_form():
+    # Fresh model, constant input X: frame 0 seeds (w_init, X, v_init) -> w = 1; afterwards
+    # mu_t = X exactly, w_0 = 1 exactly, v_t = max(v_min, (1-alpha)^t v_init), mask 0.
+    p = _params(Kc=3, Kd=3)
+    H, W = 2, 3
+    rng = np.random.default_rng(0)
+    rgb = rng.integers(0, 256, (H, W, 3)).astype(np.uint8)
+    D = rng.integers(200, 9000, (H, W)).astype(np.uint16)
+    g = GmmRef(H, W, p)
+    a = 1.0 - float(np.float32(p.alpha))
+    for t in range(520):
+        m = g.step(rgb, D)
+        assert not m.any()
+        st = g.state_planes()
+        n = t  # updates after the seeding frame
+        assert np.all(st["w_c"][0] == 1) and np.all(st["w_c"][1:] == 0)
+        assert np.all(st["w_d"][0] == 1) and np.all(st["w_d"][1:] == 0)
+        np.testing.assert_array_equal(st["mu_c"][0], np.moveaxis(rgb, -1, 0).astype(np.float32))
+        np.testing.assert_array_equal(st["mu_d"][0], depth_q8(D).astype(np.float32))
+        vc = max(p.v_min_c, a ** n * p.v_init_c)
+        vd = max(p.v_min_d, a ** n * p.v_init_d)
+        np.testing.assert_allclose(st["v_c"][0], vc, rtol=1e-4)
+        np.testing.assert_allclose(st["v_d"][0], vd, rtol=1e-4)
+    # the floors bind after ln(v_min/v_init)/ln(a) frames (about 401 colour, 320 depth)
+    assert np.all(g.state_planes()["v_c"][0] == np.float32(p.v_min_c))
+    assert np.all(g.state_planes()["v_d"][0] == np.float32(p.v_min_d))
+
+
+def test_constant_frame_from_offset_mean_closed_form():
+    # Gaussian 0 starts at mu_0 = X + Delta_0 within lambda sigma; others far and weak.
+    # Closed forms (a = 1 - alpha): mu_t - X = a^t Delta_0,
+    # v_t = a^t (v_0 + |Delta_0|^2 a (1 - a^t)), w_t = 1 - a^t (1 - w_0).
+    p = _params(Kc=3, Kd=1)
+    X = np.array([120.0, 80.0, 60.0])
+    deltas = np.array([[3.0, -2.0, 1.0], [0.5, 0.5, 0.5], [-6.0, 4.0, 2.0], [0.0, 0.0, 7.0]])
+    v0, w0 = 400.0, 0.6
+    n = len(deltas)
+    g = GmmRef(1, n, p)
+    st = g.state_planes()
+    st = dict(st)
+    st["w_c"] = np.array([[[w0] * n], [[0.3] * n], [[0.1] * n]], np.float32)
+    mu = np.zeros((3, 3, 1, n), np.float32)
+    for i in range(n):
+        mu[0, :, 0, i] = X + deltas[i]
+        mu[1, :, 0, i] = [250, 250, 250]
+        mu[2, :, 0, i] = [0, 250, 0]
+    st["mu_c"] = mu
+    st["v_c"] = np.array([[[v0] * n], [[100.0] * n], [[100.0] * n]], np.float32)
+    g.set_state_planes(st)
+    rgb = np.broadcast_to(X.astype(np.uint8), (1, n, 3)).copy()
+    D = np.zeros((1, n), np.uint16)
+    a = 1.0 - float(np.float32(p.alpha))
+    for t in range(1, 200):
+        g.step(rgb, D)
+        s = g.state_planes()
+        at = a ** t
+        exp_mu = X[None, :] + at * deltas
+        np.testing.assert_allclose(s["mu_c"][0, :, 0, :].T, exp_mu, rtol=1e-4, atol=1e-4)
+        d2 = (deltas ** 2).sum(1)
+        exp_v = at * (v0 + d2 * a * (1 - at))
+        np.testing.assert_allclose(s["v_c"][0, 0], exp_v, rtol=1e-4)
+        np.testing.assert_allclose(s["w_c"][0, 0], 1 - at * (1 - w0), rtol=1e-5)
+        np.testing.assert_allclose(s["w_c"][1, 0], at * 0.3, rtol=1e-4)
+
+
+def _stauffer_grimson_rgb(state, rgb, p):
+    """The textbook colour-only test and update, written in its own form (float64):
+    background = leading Gaussians whose weights first exceed T; the pixel is background
+    iff it lies within lambda sigma of one of them.  Update:
+    w <- (1-alpha) w + alpha M;  mu <- (1-rho) mu + rho X;  s2 <- (1-rho) s2 + rho |X-mu|^2."""
+    w, mu, v = state["w_c"].astype(np.float64), state["mu_c"].astype(np.float64), state["v_c"].astype(np.float64)
+    K, H, W = w.shape
+    X = np.moveaxis(rgb.astype(np.float64), -1, 0)
+    fg = np.zeros((H, W), bool)
+    nw, nmu, nv = w.copy(), mu.copy(), v.copy()
+    lam, al = float(p.lam), float(np.float32(p.alpha))
+    for y in range(H):
+        for x in range(W):
+            ww, mm, vv = w[:, y, x], mu[:, :, y, x], v[:, y, x]
+            if ww[0] > 0:
+                csum, B = 0.0, int((ww > 0).sum())
+                for k in range(K):
+                    csum += ww[k]
+                    if csum > p.T_bg:
+                        B = k + 1
+                        break
+                dist2 = ((X[:, y, x][None] - mm) ** 2).sum(1)
+                fg[y, x] = not any(dist2[k] < lam * lam * vv[k] for k in range(B))
+            match = [k for k in range(K) if ww[k] > 0 and ((X[:, y, x] - mm[k]) ** 2).sum() < lam * lam * vv[k]]
+            Mv = np.zeros(K)
+            if match:
+                k = match[0]
+                Mv[k] = 1
+                newmu = (1 - al) * mm[k] + al * X[:, y, x]
+                s2 = (1 - al) * vv[k] + al * ((X[:, y, x] - newmu) ** 2).sum()
+                nmu[k, :, y, x] = newmu
+                nv[k, y, x] = max(s2, p.v_min_c)
+                nw_ = (1 - al) * ww + al * Mv
+            else:
+                nw_ = (1 - al) * ww
+                nw_[K - 1] = p.w_init
+                nmu[K - 1, :, y, x] = X[:, y, x]
+                nv[K - 1, y, x] = p.v_init_c
+            nw_ = nw_ / nw_.sum()
+            keys = nw_ / np.sqrt(nv[:, y, x])
+            order = sorted(range(K), key=lambda k: -keys[k])
+            nw[:, y, x] = nw_[order]
+            nmu[:, :, y, x] = nmu[order, :, y, x]
+            nv[:, y, x] = nv[order, y, x]
+    return fg, nw, nmu, nv
+
+
+@pytest.mark.parametrize("mode", ["no_depth", "zero_depth_weight"])
+def test_reduces_to_stauffer_grimson_without_depth(mode):
+    p = _params(Kc=3, Kd=3, w_depth=0.0 if mode == "zero_depth_weight" else 1.0)
+    sc = Scene(preset("gmm_320x240", H=12, W=16, n_objects=2))
+    g = GmmRef(12, 16, p, dtype=np.float64)
+    for t in range(40):
+        rgb, D, _ = sc.frame(t)
+        if mode == "no_depth":
+            D = np.zeros_like(D)
+        before = {k: v.copy() if isinstance(v, np.ndarray) else v for k, v in g.state_planes().items()}
+        m = g.step(rgb, D)
+        fg, nw, nmu, nv = _stauffer_grimson_rgb(before, rgb, p)
+        if t > 0:
+            np.testing.assert_array_equal(m == 255, fg, err_msg=f"frame {t}")
+        s = g.state_planes()
+        # the two algebraic forms round differently; a formula slip would show at O(alpha)
+        np.testing.assert_allclose(s["w_c"], nw, rtol=1e-7, atol=1e-10)
+        np.testing.assert_allclose(s["mu_c"], nmu, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(s["v_c"], nv, rtol=1e-7)
+
+
+def test_invariants_on_moving_scene():
+    p = _params(Kc=5, Kd=5)
+    sc = Scene(preset("hd_1280x720", H=48, W=64))
+    g = GmmRef(48, 64, p)
+    for t in range(60):
+        rgb, D, _ = sc.frame(t)
+        g.step(rgb, D)
+        s = g.state_planes()
+        for w, v, vmin in ((s["w_c"], s["v_c"], p.v_min_c), (s["w_d"], s["v_d"], p.v_min_d)):
+            used = w[0] > 0
+            assert np.all(np.abs(w.sum(0)[used] - 1) <= 1e-6)
+            assert np.all(v >= np.float32(vmin))
+            assert np.all(w >= 0)
+            key = w / np.sqrt(v)
+            assert np.all(np.diff(key, axis=0) <= 0)      # ranked by w/sigma, descending
+        assert np.all(s["w_c"][0] > 0)                      # colour model always has data
+
+
+def test_static_noise_free_scene_gives_empty_mask():
+    cfg = preset("gmm_320x240", H=24, W=32, n_objects=0, rgb_noise=0.0, depth_noise_mm=0.0,
+                 hole_frac=0.0)
+    sc = Scene(cfg)
+    g = GmmRef(24, 32, _params())
+    for t in range(30):
+        rgb, D, _ = sc.frame(t)
+        assert not g.step(rgb, D).any()
+
+
+def test_colour_camouflage_needs_depth():
+    # An object whose colour equals the background but 600 mm nearer: foreground only
+    # when the depth model takes part (the case Sec. 5 reports as the biggest gain).
+    H, W = 20, 20
+    rng = np.random.default_rng(5)
+    bg = rng.integers(60, 200, (H, W, 3)).astype(np.uint8)
+    D = np.full((H, W), 2000, np.uint16)
+    obj = np.zeros((H, W), bool)
+    obj[5:12, 6:14] = True
+    res = {}
+    for use_depth in (True, False):
+        g = GmmRef(H, W, _params())
+        for t in range(40):
+            g.step(bg, D if use_depth else np.zeros_like(D))
+        D2 = D.copy()
+        D2[obj] = 1400
+        m = g.step(bg, D2 if use_depth else np.zeros_like(D2))
+        res[use_depth] = m
+    assert np.all(res[True][obj] == 255) and not res[True][~obj].any()
+    assert not res[False].any()
+
+
+def test_invalid_depth_leaves_depth_model_untouched():
+    g = GmmRef(4, 4, _params())
+    sc = Scene(preset("gmm_320x240", H=4, W=4, n_objects=0))
+    for t in range(5):
+        g.step(*sc.frame(t)[:2])
+    before = {k: np.array(v, copy=True) for k, v in g.state_planes().items() if k != "t"}
+    rgb, D, _ = sc.frame(5)
+    D[1, 2] = 0
+    g.step(rgb, D)
+    after = g.state_planes()
+    for k in ("w_d", "mu_d", "v_d"):
+        np.testing.assert_array_equal(after[k][:, 1, 2], before[k][:, 1, 2])
+    assert not np.array_equal(after["v_d"][:, 0, 0], before["v_d"][:, 0, 0])  # valid: updated
+
+
+def _scalar_step(state, rgb, D, p):
+    """Brute force: one pixel at a time in Python float32 scalars, following the same
+    definitions.  Used on tiny images only."""
+    f = np.float32
+    a, al, lam2 = f(1) - f(p.alpha), f(p.alpha), f(p.lam) * f(p.lam)
+    Kc, H, W = state["w_c"].shape
+    out = {k: np.array(v, copy=True) for k, v in state.items() if k != "t"}
+    mask = np.zeros((H, W), np.uint8)
+    q8 = depth_q8(D)
+    for y in range(H):
+        for x in range(W):
+            models = [("c", [f(v) for v in rgb[y, x]], True, f(p.w_init), f(p.v_init_c), f(p.v_min_c)),
+                      ("d", [f(q8[y, x])], D[y, x] > 0, f(p.w_init), f(p.v_init_d), f(p.v_min_d))]
+            terms = []
+            for name, X, active, wi, vi, vmin in models:
+                w = [f(v) for v in out["w_" + name][:, y, x]]
+                mu = ([[f(c) for c in out["mu_c"][k, :, y, x]] for k in range(Kc)] if name == "c"
+                      else [[f(out["mu_d"][k, y, x])] for k in range(len(w))])
+                v = [f(s) for s in out["v_" + name][:, y, x]]
+                K = len(w)
+                q = []
+                for k in range(K):
+                    d2 = f(0)
+                    for c in range(len(X)):
+                        e = f(X[c] - mu[k][c])
+                        d2 = f(e * e) if c == 0 else f(d2 + f(e * e))
+                    q.append(f(d2 / v[k]))
+                if w[0] > 0 and active:
+                    cum, B = f(0), sum(1 for s in w if s > 0)
+                    for k in range(K):
+                        cum = f(cum + w[k])
+                        if cum > f(p.T_bg):
+                            B = k + 1
+                            break
+                    terms.append((name, min(q[:B])))
+                if not active:
+                    continue
+                ks = next((k for k in range(K) if w[k] > 0 and q[k] < lam2), None)
+                w = [f(a * s) for s in w]
+                if ks is not None:
+                    w[ks] = f(w[ks] + al)
+                    mu[ks] = [f(m + f(al * f(X[c] - m))) for c, m in enumerate(mu[ks])]
+                    d2 = f(0)
+                    for c in range(len(X)):
+                        e = f(X[c] - mu[ks][c])
+                        d2 = f(e * e) if c == 0 else f(d2 + f(e * e))
+                    v[ks] = max(f(v[ks] + f(al * f(d2 - v[ks]))), vmin)
+                else:
+                    w[K - 1], mu[K - 1], v[K - 1] = wi, list(X), vi
+                S = w[0]
+                for k in range(1, K):
+                    S = f(S + w[k])
+                w = [f(s / S) for s in w]
+                keys = [f(w[k] / np.sqrt(v[k])) for k in range(K)]
+                order = sorted(range(K), key=lambda k: -keys[k])   # Python's sort is stable
+                out["w_" + name][:, y, x] = [w[k] for k in order]
+                out["v_" + name][:, y, x] = [v[k] for k in order]
+                if name == "c":
+                    out["mu_c"][:, :, y, x] = [mu[k] for k in order]
+                else:
+                    out["mu_d"][:, y, x] = [mu[k][0] for k in order]
+            Z = None
+            for name, delta in terms:
+                tterm = f(delta - lam2) if name == "c" else f(f(p.w_depth) * f(delta - lam2))
+                Z = tterm if Z is None else f(Z + tterm)
+            mask[y, x] = 255 if (Z is not None and Z >= 0) else 0
+    return mask, out
+
+
+def test_vectorised_equals_scalar_brute_force():
+    p = _params(Kc=3, Kd=2)
+    sc = Scene(preset("gmm_320x240", H=5, W=6, n_objects=1))
+    g = GmmRef(5, 6, p)
+    for t in range(25):
+        rgb, D, _ = sc.frame(t)
+        st = {k: np.array(v, copy=True) if k != "t" else v for k, v in g.state_planes().items()}
+        m = g.step(rgb, D)
+        m2, out = _scalar_step(st, rgb, D, p)
+        np.testing.assert_array_equal(m, m2)
+        s = g.state_planes()
+        for k in out:
+            np.testing.assert_array_equal(s[k], out[k], err_msg=f"{k} frame {t}")

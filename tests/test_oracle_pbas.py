@@ -1,0 +1,214 @@
+"""Pins for the PBAS oracle (Sec. 3.2 and the base PBAS rules it adapts).
+
+Checked against: hand-derived frames (tests/golden), invariants of the model (bounds of
+R and T, S = sum of D, sample provenance), the update decisions against the Philox words
+(pinned separately against the ROCm library), update statistics, and scenes whose
+answer is known (static scene, colour camouflage)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle.depth import depth_q8
+from oracle.pbas import NB_DX, NB_DY, PbasParams, PbasRef, pbas_draws
+from synth import Scene, preset
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "pbas_hand_cases.json")
+
+
+def test_hand_derived_frames():
+    gold = json.load(open(GOLD))
+    pr = dict(gold["params"])
+    pr["R_lower"] = tuple(pr["R_lower"])
+    for seed in (1, 2, 3, 0xDEADBEEF):       # the answer must not depend on the draws
+        ref = PbasRef(1, 1, PbasParams(seed=seed, **pr))
+        for fr in gold["frames"]:
+            m = ref.step(np.array(fr["rgb"], np.uint8).reshape(1, 1, 3),
+                         np.array([[fr["D"]]], np.uint16))
+            assert m[0, 0] == fr["mask"], fr["note"]
+            if "expect_samples" in fr:
+                for j in range(4):
+                    assert sorted(ref.samples[:, 0, 0, j].tolist()) == fr["expect_samples"][j], fr["note"]
+                    assert sorted(ref.D[:, 0, 0, j].tolist()) == fr["expect_dhist"][j], fr["note"]
+                assert ref.S[0, 0].tolist() == fr["expect_S"]
+                assert ref.R[0, 0].tolist() == [np.float32(v) for v in fr["expect_R"]]
+                assert ref.T[0, 0].tolist() == fr["expect_T"]
+
+
+def _run(cfg, params, frames, audit=None):
+    sc = Scene(cfg)
+    ref = PbasRef(cfg.H, cfg.W, params)
+    masks = []
+    for t in range(frames):
+        rgb, D, _ = sc.frame(t)
+        before = (ref.T.copy(), ref.samples.copy(), ref.D.copy())
+        masks.append(ref.step(rgb, D))
+        if audit is not None:
+            audit(ref, t, rgb, D, before)
+    return ref, masks
+
+
+def test_invariants_and_provenance():
+    cfg = preset("pbas_640x480", H=18, W=22)
+    p = PbasParams(N=8)
+    seen = np.zeros((256, 18, 22, 4), bool)      # values observed per pixel and channel
+    seen[0, :, :, 3] = True                      # depth byte 0 = "no depth recorded"
+
+    def audit(ref, t, rgb, D, before):
+        I = ref.frame_value(rgb, D)
+        yy, xx = np.mgrid[0:18, 0:22]
+        for j in range(4):
+            seen[I[..., j], yy, xx, j] = True
+        # every sample byte at a pixel is a value that pixel has shown (never a neighbour's)
+        for k in range(min(p.N, t + 1)):          # slots >= t+1 are still empty in init
+            for j in range(4):
+                assert seen[ref.samples[k, :, :, j], yy, xx, j].all(), (t, k, j)
+        assert np.all(ref.R >= np.array(p.R_lower, np.float32))
+        assert np.all((ref.T >= p.T_lower) & (ref.T <= p.T_upper))
+        np.testing.assert_array_equal(ref.S, ref.D.astype(np.int64).sum(0))
+
+    _run(cfg, p, 70, audit)
+
+
+def test_update_decisions_follow_draws():
+    cfg = preset("pbas_640x480", H=10, W=12)
+    p = PbasParams(N=6, seed=77)
+
+    def audit(ref, t, rgb, D, before):
+        if t < p.N:
+            return
+        T_prev, samp_prev, D_prev = before
+        w0, w1 = pbas_draws(10, 12, t, p.seed)
+        u0 = (w0 >> 16).astype(np.float64) / 65536.0
+        u1 = (w1 >> 16).astype(np.float64) / 65536.0
+        active = np.ones((10, 12, 4), bool)
+        active[..., 3] = D > 0
+        bg = active & ~ref.last_F
+        # the decision uses the rate T from before this frame
+        np.testing.assert_array_equal(ref.last_self, bg & (u0 * T_prev.astype(np.float64) < 1.0))
+        np.testing.assert_array_equal(ref.last_nb, bg & (u1 * T_prev.astype(np.float64) < 1.0))
+        I = ref.frame_value(rgb, D)
+        k = ((w0 & 0xFFFF).astype(np.int64) * p.N) >> 16
+        ys, xs, js = np.nonzero(ref.last_self)
+        assert np.all(ref.samples[k[ys, xs, js], ys, xs, js] == I[ys, xs, js])
+        # a pixel's D history changes only in the slot its own self-update chose
+        changed = ref.D != D_prev
+        n, ys, xs, js = np.nonzero(changed)
+        assert np.all(ref.last_self[ys, xs, js]) and np.all(k[ys, xs, js] == n)
+
+    _run(cfg, p, 40, audit)
+
+
+def test_neighbour_writes_gathered_independently():
+    # Recompute frame t's neighbour writes as a gather (each pixel collects the writes
+    # aimed at it) and compare with the oracle's scatter.
+    cfg = preset("pbas_640x480", H=9, W=11, n_objects=1)
+    p = PbasParams(N=5, T_lower=1.0, T_upper=3.0, seed=5)
+    sc = Scene(cfg)
+    ref = PbasRef(9, 11, p)
+    for t in range(30):
+        rgb, D, _ = sc.frame(t)
+        prev = ref.samples.copy()
+        ref.step(rgb, D)
+        if t < p.N:
+            continue
+        I = ref.frame_value(rgb, D)
+        w0, w1 = ref.last_draws
+        expect = prev.copy()
+        k0 = ((w0 & 0xFFFF).astype(np.int64) * p.N) >> 16
+        ys, xs, js = np.nonzero(ref.last_self)
+        expect[k0[ys, xs, js], ys, xs, js] = I[ys, xs, js]
+        direc = (w1 >> 13) & 7
+        k1 = ((w1 & 0x1FFF).astype(np.int64) * p.N) >> 13
+        for y in range(9):
+            for x in range(11):
+                for oy in (-1, 0, 1):
+                    for ox in (-1, 0, 1):
+                        sy, sx = y + oy, x + ox               # a possible source
+                        if (ox, oy) == (0, 0) or not (0 <= sy < 9 and 0 <= sx < 11):
+                            continue
+                        for j in range(4):
+                            if not ref.last_nb[sy, sx, j]:
+                                continue
+                            d = direc[sy, sx, j]
+                            if (sx + NB_DX[d], sy + NB_DY[d]) != (x, y):
+                                continue
+                            if j == 3 and D[y, x] == 0:
+                                continue
+                            expect[k1[sy, sx, j], y, x, j] = I[y, x, j]
+        np.testing.assert_array_equal(ref.samples, expect, err_msg=f"frame {t}")
+
+
+def test_update_rate_and_uniform_choices():
+    # Fixed T: the self-update fires with probability 1/T; slots and directions uniform.
+    cfg = preset("pbas_640x480", H=64, W=64, n_objects=0, illumination=False, camouflage=False)
+    T0 = 4.0
+    p = PbasParams(N=16, T_lower=T0, T_upper=T0, seed=123)
+    sc = Scene(cfg)
+    ref = PbasRef(64, 64, p)
+    fires = trials = 0
+    slots = np.zeros(p.N, np.int64)
+    dirs = np.zeros(8, np.int64)
+    for t in range(40):
+        ref.step(*sc.frame(t)[:2])
+        if t < p.N:
+            continue
+        bg = ~ref.last_F & np.ones_like(ref.last_F)
+        bg[..., 3] &= sc.frame(t)[1] > 0
+        trials += int(bg.sum())
+        fires += int(ref.last_self.sum())
+        w0, w1 = ref.last_draws
+        slots += np.bincount((((w0 & 0xFFFF).astype(np.int64) * p.N) >> 16)[ref.last_self], minlength=p.N)
+        dirs += np.bincount(((w1 >> 13) & 7)[ref.last_nb].astype(np.int64), minlength=8)
+    rate = fires / trials
+    sd = np.sqrt(0.25 * 0.75 / trials)
+    assert abs(rate - 1 / T0) < 5 * sd
+    for c in (slots, dirs):
+        e = c.sum() / len(c)
+        assert ((c - e) ** 2 / e).sum() < 3 * len(c) + 30
+
+
+def test_static_noise_free_scene_gives_empty_mask():
+    cfg = preset("pbas_640x480", H=16, W=20, n_objects=0, illumination=False, camouflage=False,
+                 rgb_noise=0.0, depth_noise_mm=0.0, hole_frac=0.0)
+    p = PbasParams(N=6)
+    _, masks = _run(cfg, p, 25)
+    assert not any(m.any() for m in masks)
+
+
+def test_colour_camouflage_detected_only_with_depth():
+    H, W = 24, 24
+    rng = np.random.default_rng(9)
+    bg = rng.integers(40, 220, (H, W, 3)).astype(np.uint8)
+    D = np.full((H, W), 3000, np.uint16)
+    obj = np.zeros((H, W), bool)
+    obj[6:16, 8:18] = True
+    out = {}
+    for use_depth in (True, False):
+        ref = PbasRef(H, W, PbasParams(N=10))
+        Dm = D if use_depth else np.zeros_like(D)
+        for t in range(20):
+            ref.step(bg, Dm)
+        D2 = D.copy()
+        D2[obj] = 2400                      # 600 mm nearer, colour unchanged
+        out[use_depth] = ref.step(bg, D2 if use_depth else np.zeros_like(D2))
+    assert np.all(out[True][obj] == 255) and not out[True][~obj].any()
+    assert not out[False].any()
+
+
+def test_invalid_depth_pixel_skips_depth_channel():
+    cfg = preset("pbas_640x480", H=8, W=8, n_objects=0, illumination=False, camouflage=False)
+    p = PbasParams(N=4, T_lower=1.0, T_upper=1.0)
+    sc = Scene(cfg)
+    ref = PbasRef(8, 8, p)
+    for t in range(8):
+        ref.step(*sc.frame(t)[:2])
+    rgb, D, _ = sc.frame(8)
+    D[:] = 0
+    before = (ref.samples[..., 3].copy(), ref.D[..., 3].copy(), ref.R[..., 3].copy(), ref.T[..., 3].copy())
+    ref.step(rgb, D)
+    after = (ref.samples[..., 3], ref.D[..., 3], ref.R[..., 3], ref.T[..., 3])
+    for b, a in zip(before, after):
+        np.testing.assert_array_equal(a, b)
+    assert not ref.last_F[..., 3].any()
