@@ -1,0 +1,49 @@
+// Device helpers shared by the GMM and PBAS kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fgs {
+
+// 8-bit depth code (Sec. 4.1-4.2): 0 = no depth; otherwise the round-half-up
+// rescale of millimetres to `full_scale_mm`, clamped to [1, 255].
+__device__ __forceinline__ uint32_t depth_code(uint32_t d_mm, uint32_t full_scale_mm) {
+    if (d_mm == 0u) return 0u;
+    uint32_t q = (255u * d_mm + (full_scale_mm >> 1)) / full_scale_mm;
+    q = q < 1u ? 1u : q;
+    return q > 255u ? 255u : q;
+}
+
+struct U32x4 {
+    uint32_t v[4];
+};
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of the keyed bijection on a
+// 128-bit counter.  Each round forms the two 64-bit products of counter words
+// 0 and 2 with the round multipliers and permutes their halves with words 1
+// and 3 and the key; the key advances by the Weyl increments between rounds.
+__device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    U32x4 r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+}  // namespace fgs

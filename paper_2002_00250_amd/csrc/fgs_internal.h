@@ -1,0 +1,96 @@
+// Internal declarations of libfgs: model object, kernel argument blocks and the
+// host-side launch wrappers each kernel file exports to the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fgs.h"
+
+namespace fgs {
+
+// ---------------------------------------------------------------- GMM ----
+// Device layout: per pixel, Kc "core" float4 planes (w, mu_r, mu_g, mu_b) of the
+// colour Gaussians, then E "extra" float4 planes holding, in order, v_c[Kc],
+// w_d[Kd], mu_d[Kd], v_d[Kd] (padded).  Plane i of pixel p is at state[i*npix + p]:
+// every access is one 16-byte load or store per lane, a wavefront touching 1 KiB
+// of contiguous memory.
+inline int gmm_extra_planes(int Kc, int Kd) { return (Kc + 3 * Kd + 3) / 4; }
+inline int gmm_planes(int Kc, int Kd) { return Kc + gmm_extra_planes(Kc, Kd); }
+bool gmm_supported(int Kc, int Kd);
+
+struct GmmConsts {
+    float alpha, lam, T_bg, w_init, v_init_c, v_min_c, v_init_d, v_min_d, w_depth;
+    uint32_t depth_max_mm;
+};
+
+struct GmmStepArgs {
+    float4* state;
+    uint8_t* mask;
+    const uint8_t* rgb;
+    const uint8_t* depth;  // uint16 rows, addressed in bytes
+    int64_t rgb_stride, depth_stride;
+    int32_t H, W, npix;
+    GmmConsts c;
+};
+
+hipError_t gmm_launch_init(float4* state, int Kc, int Kd, int npix, const GmmConsts& c,
+                           hipStream_t s);
+hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s);
+// canonical planar float32 <-> device layout
+hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, int npix,
+                             hipStream_t s);
+hipError_t gmm_launch_import(float4* state, const float* in, int Kc, int Kd, int npix,
+                             hipStream_t s);
+
+// --------------------------------------------------------------- PBAS ----
+// Device layout: samples[N] and dhist[N] uint32 planes (bytes R,G,B,depth), R and
+// T as one float4 per pixel, S as four uint16 per pixel (uint2), `last` = the
+// pixel's previous RGBD8 word, and two ping-pong planes of neighbour-update
+// intents (uint64 per pixel: 16 bits per channel = fire | dir<<12 | slot).
+struct PbasConsts {
+    int32_t N, min_matches;
+    float R_incdec, R_scale, T_inc, T_dec, T_lower, T_upper;
+    float R_lower[4];
+    uint32_t depth_max_mm;
+    uint32_t key0, key1;
+};
+
+struct PbasPlanes {
+    uint32_t* samples;
+    uint32_t* dhist;
+    float4* R;
+    float4* T;
+    uint2* S;
+    uint32_t* last;
+    uint64_t* intents[2];
+    uint8_t* mask;
+};
+
+struct PbasStepArgs {
+    PbasPlanes m;
+    const uint8_t* rgb;
+    const uint8_t* depth;
+    int64_t rgb_stride, depth_stride;
+    int32_t H, W, npix;
+    uint32_t t;            // frame index
+    int32_t apply_pending; // intents of frame t-1 still to be applied
+    PbasConsts c;
+};
+
+hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConsts& c,
+                                  hipStream_t s);
+hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s);
+hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, int N,
+                             hipStream_t s);
+hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out, hipStream_t s);
+hipError_t pbas_launch_import(const PbasPlanes& m, int npix, int N, const uint8_t* in,
+                              hipStream_t s);
+
+// -------------------------------------------------------- diagnostics ----
+hipError_t diag_launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
+                              hipStream_t s);
+hipError_t diag_launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+}  // namespace fgs

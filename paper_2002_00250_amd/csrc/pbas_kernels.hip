@@ -1,0 +1,354 @@
+// RGB-D Pixel-Based Adaptive Segmenter: one classify-and-update kernel per frame
+// (Sec. 3.2).  Four per-channel PBAS instances (R, G, B, depth code) share a
+// sample buffer of N RGBD8 words per pixel (Sec. 4.2 packing).
+//
+// Neighbour updates without races or atomics.  At frame t a background pixel x
+// may write its 8-neighbour y's own value I(y,t) into a random sample of y.  All
+// such writes into y carry the same value and only y itself touches its D
+// history, so their order does not matter; what matters is that y's
+// classification at frame t still sees the model of frame t-1.  Each pixel
+// therefore records its intent (fire, direction, slot per channel, 64 bits) at
+// frame t, and at frame t+1 every pixel first gathers the intents of its eight
+// neighbours from a 64x4 tile plus 1-pixel halo staged in LDS and applies the
+// writes aimed at it, using its stored previous value, before it classifies.
+// `pbas_flush` applies pending intents when the state is read out.
+//
+// Tile shape: a 256-lane workgroup covers 64 columns x 4 rows, one wavefront per
+// row, one pixel per lane, so each sample-plane access of a wavefront is 256
+// contiguous bytes.
+#include "device_common.h"
+#include "fgs_internal.h"
+
+namespace fgs {
+
+namespace {
+
+constexpr int kTileW = 64;
+constexpr int kTileH = 4;
+constexpr int kBlock = kTileW * kTileH;
+constexpr int kHaloW = kTileW + 2;
+constexpr int kHaloH = kTileH + 2;
+
+// 8-neighbourhood indexed by the 3-bit direction field: (dx, dy) =
+// (-1,-1) (0,-1) (1,-1) (-1,0) (1,0) (-1,1) (0,1) (1,1).  The table is point
+// symmetric: the opposite of direction d is 7 - d.
+__device__ __forceinline__ int nb_dx(int d) { return (d == 0 || d == 3 || d == 5) ? -1 : ((d == 1 || d == 6) ? 0 : 1); }
+__device__ __forceinline__ int nb_dy(int d) { return d < 3 ? -1 : (d < 5 ? 0 : 1); }
+
+__device__ __forceinline__ uint8_t* byte_at(uint32_t* plane0, int64_t npix, int slot, int p, int j) {
+    return reinterpret_cast<uint8_t*>(plane0 + (int64_t)slot * npix + p) + j;
+}
+
+// Stage the intents of the tile and its 1-pixel halo into LDS.
+__device__ __forceinline__ void stage_intents(uint64_t* lds, const uint64_t* __restrict__ intents,
+                                              int x0, int y0, int H, int W) {
+    for (int i = threadIdx.x; i < kHaloW * kHaloH; i += kBlock) {
+        const int gx = x0 + (i % kHaloW) - 1;
+        const int gy = y0 + (i / kHaloW) - 1;
+        uint64_t v = 0;
+        if (gx >= 0 && gx < W && gy >= 0 && gy < H) v = intents[(int64_t)gy * W + gx];
+        lds[i] = v;
+    }
+}
+
+// Apply the neighbour writes aimed at pixel (lx,ly) of the tile: byte stores of
+// the pixel's previous value into the chosen sample slots.
+__device__ __forceinline__ void apply_pending(const uint64_t* lds, int lx, int ly, uint32_t lastw,
+                                              uint32_t* samples, int64_t npix, int p, int N) {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        // the source x sits at offset delta[d] from this pixel and must have fired
+        // in the opposite direction 7 - d to reach it
+        const int ox = nb_dx(d), oy = nb_dy(d);
+        const uint64_t v = lds[(ly + 1 + oy) * kHaloW + (lx + 1 + ox)];
+        if (v == 0) continue;
+        const uint32_t want = 0x8u | (uint32_t)(7 - d);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t f = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
+            if ((f >> 12) != want) continue;
+            const uint32_t val = (lastw >> (8 * j)) & 0xFFu;
+            const int slot = (int)(f & 0x3Fu);
+            if ((j == 3 && val == 0u) || slot >= N) continue;  // y had no depth at that frame
+            *byte_at(samples, npix, slot, p, j) = (uint8_t)val;
+        }
+    }
+}
+
+// One updating frame.  The pixel's N sample words live in registers between one
+// dense coalesced read and one dense coalesced write of the sample planes (the
+// random slot replacements are applied in registers), so no sample plane sees a
+// partial-line write.  The Philox draws and the 1/T tests do not depend on the
+// classification, so the candidate self-update slots are known first and their
+// D-history bytes are fetched before the samples, off the critical path.
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
+    __shared__ uint64_t lds[kHaloW * kHaloH];
+    const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
+    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+    const int x = x0 + lx, y = y0 + ly;
+    const int W = a.W, H = a.H;
+    const int64_t npix = a.npix;
+    const int N = a.c.N;
+
+    if (a.apply_pending) {
+        stage_intents(lds, a.m.intents[(a.t - 1u) & 1u], x0, y0, H, W);
+        __syncthreads();
+    }
+    if (x >= W || y >= H) return;
+    const int p = y * W + x;
+
+    // Ingest.
+    const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
+    const uint32_t dmm = *reinterpret_cast<const uint16_t*>(a.depth + (int64_t)y * a.depth_stride + 2 * x);
+    const bool valid = dmm > 0u;
+    int I[4];
+    I[0] = px[0];
+    I[1] = px[1];
+    I[2] = px[2];
+    I[3] = (int)depth_code(dmm, a.c.depth_max_mm);
+    const uint32_t Iw = (uint32_t)I[0] | ((uint32_t)I[1] << 8) | ((uint32_t)I[2] << 16) | ((uint32_t)I[3] << 24);
+
+    const float4 Rv = a.m.R[p];
+    const float4 Tv = a.m.T[p];
+    const uint2 Sv = a.m.S[p];
+    const uint32_t lastw = a.m.last[p];
+    float R[4] = {Rv.x, Rv.y, Rv.z, Rv.w};
+    float T[4] = {Tv.x, Tv.y, Tv.z, Tv.w};
+    int S[4] = {(int)(Sv.x & 0xFFFFu), (int)(Sv.x >> 16), (int)(Sv.y & 0xFFFFu), (int)(Sv.y >> 16)};
+    const bool active[4] = {true, true, true, valid};
+
+    // Two Philox blocks: 0 drives the self-update, 1 the neighbour update.
+    const U32x4 w0 = philox4x32_10((uint32_t)p, a.t, 0u, 0u, a.c.key0, a.c.key1);
+    const U32x4 w1 = philox4x32_10((uint32_t)p, a.t, 1u, 0u, a.c.key0, a.c.key1);
+    const float inv16 = 1.0f / 65536.0f;
+
+    // Self-update candidates: the 1/T test with T from before this frame.
+    bool cand[4];
+    int ks[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t a0 = w0.v[j];
+        cand[j] = active[j] && (float)(a0 >> 16) * inv16 * T[j] < 1.0f;
+        ks[j] = (int)(((a0 & 0xFFFFu) * (uint32_t)N) >> 16);
+    }
+    int dold[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dold[j] = cand[j] ? (int)*byte_at(a.m.dhist, npix, ks[j], p, j) : 0;
+
+    // Frame t-1's neighbour writes into this pixel, before it is classified.
+    if (a.apply_pending) apply_pending(lds, lx, ly, lastw, a.m.samples, npix, p, N);
+
+    uint32_t sm[NMAX];
+    const uint32_t* sp = a.m.samples + p;  // may alias the pending byte stores above
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) sm[k] = k < N ? sp[(int64_t)k * npix] : 0u;
+
+    // Classification: an integer distance d is within R iff d <= ceil(R) - 1.
+    int thr[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) thr[j] = (int)fminf(ceilf(R[j]), 256.0f) - 1;
+    int cnt[4] = {0, 0, 0, 0};
+    int dmn[4] = {255, 255, 255, 255};
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+        if (k < N) {
+            const uint32_t s = sm[k];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int dd = abs((int)((s >> (8 * j)) & 0xFFu) - I[j]);
+                cnt[j] += dd <= thr[j] ? 1 : 0;
+                dmn[j] = min(dmn[j], dd);
+            }
+            const int b3 = (int)(s >> 24);
+            const int dd = b3 != 0 ? abs(b3 - I[3]) : 256;  // empty depth slot: never within R
+            cnt[3] += dd <= thr[3] ? 1 : 0;
+            dmn[3] = min(dmn[3], dd);
+        }
+    }
+    bool F[4], upd[4];
+    bool fg = false;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        F[j] = active[j] && cnt[j] < a.c.min_matches;
+        fg = fg || F[j];
+        upd[j] = cand[j] && !F[j];
+    }
+    a.m.mask[p] = fg ? (uint8_t)255 : (uint8_t)0;
+
+    // Self-update: sample slot ks[j] takes I_j, its D slot takes d_min.
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+        uint32_t v = sm[k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (upd[j] && ks[j] == k) v = (v & ~(0xFFu << (8 * j))) | ((uint32_t)I[j] << (8 * j));
+        sm[k] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (upd[j]) {
+            S[j] = S[j] - dold[j] + dmn[j];
+            *byte_at(a.m.dhist, npix, ks[j], p, j) = (uint8_t)dmn[j];
+        }
+
+    // Neighbour update with probability 1/T (T from before this frame): record the intent.
+    uint64_t intent = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!active[j] || F[j]) continue;
+        const uint32_t a1 = w1.v[j];
+        if ((float)(a1 >> 16) * inv16 * T[j] < 1.0f) {
+            const int d = (int)((a1 >> 13) & 7u);
+            const int nx = x + nb_dx(d), ny = y + nb_dy(d);
+            if (nx >= 0 && nx < W && ny >= 0 && ny < H) {
+                const uint32_t slot = ((a1 & 0x1FFFu) * (uint32_t)N) >> 13;
+                intent |= (uint64_t)(0x8000u | ((uint32_t)d << 12) | slot) << (16 * j);
+            }
+        }
+    }
+
+    // Decision threshold and update rate.
+    const float rdn = 1.0f - a.c.R_incdec, rup = 1.0f + a.c.R_incdec;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        if (!active[j]) continue;
+        const float dbar = (float)S[j] / (float)N;
+        const float r = (R[j] > dbar * a.c.R_scale) ? R[j] * rdn : R[j] * rup;
+        R[j] = fmaxf(r, a.c.R_lower[j]);
+        const float tt = F[j] ? T[j] + a.c.T_inc / dbar : T[j] - a.c.T_dec / dbar;
+        T[j] = fminf(fmaxf(tt, a.c.T_lower), a.c.T_upper);
+    }
+
+    uint32_t* so = a.m.samples + p;
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k)
+        if (k < N) so[(int64_t)k * npix] = sm[k];
+    a.m.R[p] = make_float4(R[0], R[1], R[2], R[3]);
+    a.m.T[p] = make_float4(T[0], T[1], T[2], T[3]);
+    a.m.S[p] = make_uint2((uint32_t)S[0] | ((uint32_t)S[1] << 16), (uint32_t)S[2] | ((uint32_t)S[3] << 16));
+    a.m.last[p] = Iw;
+    a.m.intents[a.t & 1u][p] = intent;
+}
+
+// Frames 0..N-1: sample slot t takes the frame; the mask is empty.
+__global__ __launch_bounds__(256) void pbas_fill_kernel(PbasStepArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.npix) return;
+    const int y = p / a.W, x = p - (p / a.W) * a.W;
+    const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
+    const uint32_t dmm = *reinterpret_cast<const uint16_t*>(a.depth + (int64_t)y * a.depth_stride + 2 * x);
+    const uint32_t Iw = (uint32_t)px[0] | ((uint32_t)px[1] << 8) | ((uint32_t)px[2] << 16) |
+                        (depth_code(dmm, a.c.depth_max_mm) << 24);
+    a.m.samples[(int64_t)a.t * a.npix + p] = Iw;
+    a.m.last[p] = Iw;
+    a.m.mask[p] = 0;
+}
+
+// Apply the intents of the last processed frame (read-out of the logical state).
+__global__ __launch_bounds__(kBlock) void pbas_flush_kernel(PbasPlanes m, int H, int W,
+                                                            uint32_t t_prev, int N) {
+    __shared__ uint64_t lds[kHaloW * kHaloH];
+    const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
+    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
+    stage_intents(lds, m.intents[t_prev & 1u], x0, y0, H, W);
+    __syncthreads();
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= W || y >= H) return;
+    const int p = y * W + x;
+    apply_pending(lds, lx, ly, m.last[p], m.samples, (int64_t)H * W, p, N);
+}
+
+__global__ void pbas_init_state_kernel(PbasPlanes m, int npix, float4 Rl, float Tl) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    m.R[p] = Rl;
+    m.T[p] = make_float4(Tl, Tl, Tl, Tl);
+}
+
+// Canonical R[4], T[4] float32 planes and S[4] uint16 planes <-> per-pixel vectors.
+__global__ void pbas_export_rts_kernel(PbasPlanes m, int npix, float* rt, uint16_t* s) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const int64_t n = npix;
+    const float4 r = m.R[p], t = m.T[p];
+    const uint2 sv = m.S[p];
+    rt[0 * n + p] = r.x; rt[1 * n + p] = r.y; rt[2 * n + p] = r.z; rt[3 * n + p] = r.w;
+    rt[4 * n + p] = t.x; rt[5 * n + p] = t.y; rt[6 * n + p] = t.z; rt[7 * n + p] = t.w;
+    s[0 * n + p] = (uint16_t)(sv.x & 0xFFFFu);
+    s[1 * n + p] = (uint16_t)(sv.x >> 16);
+    s[2 * n + p] = (uint16_t)(sv.y & 0xFFFFu);
+    s[3 * n + p] = (uint16_t)(sv.y >> 16);
+}
+
+__global__ void pbas_import_rts_kernel(PbasPlanes m, int npix, const float* rt, const uint16_t* s) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const int64_t n = npix;
+    m.R[p] = make_float4(rt[0 * n + p], rt[1 * n + p], rt[2 * n + p], rt[3 * n + p]);
+    m.T[p] = make_float4(rt[4 * n + p], rt[5 * n + p], rt[6 * n + p], rt[7 * n + p]);
+    m.S[p] = make_uint2((uint32_t)s[0 * n + p] | ((uint32_t)s[1 * n + p] << 16),
+                        (uint32_t)s[2 * n + p] | ((uint32_t)s[3 * n + p] << 16));
+}
+
+inline unsigned blocks1d(int n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConsts& c,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(pbas_init_state_kernel, dim3(blocks1d(npix)), dim3(256), 0, s, m, npix,
+                       make_float4(c.R_lower[0], c.R_lower[1], c.R_lower[2], c.R_lower[3]),
+                       c.T_lower);
+    return hipGetLastError();
+}
+
+hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
+    if ((int)a.t < a.c.N) {
+        hipLaunchKernelGGL(pbas_fill_kernel, dim3(blocks1d(a.npix)), dim3(256), 0, s, a);
+    } else {
+        const dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH);
+        const int n = a.c.N;
+        if (n <= 8) hipLaunchKernelGGL(pbas_step_kernel<8>, grid, dim3(kBlock), 0, s, a);
+        else if (n <= 16) hipLaunchKernelGGL(pbas_step_kernel<16>, grid, dim3(kBlock), 0, s, a);
+        else if (n <= 24) hipLaunchKernelGGL(pbas_step_kernel<24>, grid, dim3(kBlock), 0, s, a);
+        else if (n <= 40) hipLaunchKernelGGL(pbas_step_kernel<40>, grid, dim3(kBlock), 0, s, a);
+        else hipLaunchKernelGGL(pbas_step_kernel<64>, grid, dim3(kBlock), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, int N,
+                             hipStream_t s) {
+    const dim3 grid((W + kTileW - 1) / kTileW, (H + kTileH - 1) / kTileH);
+    hipLaunchKernelGGL(pbas_flush_kernel, grid, dim3(kBlock), 0, s, m, H, W, t_prev, N);
+    return hipGetLastError();
+}
+
+// Canonical payload: samples[N] u32, dhist[N] u32, R[4] f32, T[4] f32, S[4] u16.
+hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out, hipStream_t s) {
+    const size_t plane = (size_t)npix * 4;
+    hipError_t e = hipMemcpyAsync(out, m.samples, plane * N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(out + plane * N, m.dhist, plane * N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    float* rt = reinterpret_cast<float*>(out + 2 * plane * N);
+    uint16_t* sv = reinterpret_cast<uint16_t*>(out + 2 * plane * N + 8 * plane);
+    hipLaunchKernelGGL(pbas_export_rts_kernel, dim3(blocks1d(npix)), dim3(256), 0, s, m, npix, rt, sv);
+    return hipGetLastError();
+}
+
+hipError_t pbas_launch_import(const PbasPlanes& m, int npix, int N, const uint8_t* in,
+                              hipStream_t s) {
+    const size_t plane = (size_t)npix * 4;
+    hipError_t e = hipMemcpyAsync(m.samples, in, plane * N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(m.dhist, in + plane * N, plane * N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    const float* rt = reinterpret_cast<const float*>(in + 2 * plane * N);
+    const uint16_t* sv = reinterpret_cast<const uint16_t*>(in + 2 * plane * N + 8 * plane);
+    hipLaunchKernelGGL(pbas_import_rts_kernel, dim3(blocks1d(npix)), dim3(256), 0, s, m, npix, rt, sv);
+    return hipGetLastError();
+}
+
+}  // namespace fgs

@@ -1,0 +1,581 @@
+// libfgs runtime: the C ABI of include/fgs.h.  Owns model objects, their device
+// memory (one allocation per model, every plane 256-byte aligned), the pinned
+// staging used for host frames, and the stream each model runs on.  All
+// per-pixel work is done by the kernels in gmm_kernels.hip / pbas_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fgs.h"
+#include "fgs_internal.h"
+
+using namespace fgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fgs_status fail(fgs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+constexpr uint32_t kStateMagic = 0x53534746u;  // "FGSS"
+constexpr uint32_t kStateVersion = 1;
+constexpr size_t kHeaderBytes = 64;
+constexpr int64_t kMaxPixels = int64_t(1) << 28;
+
+struct StateHeader {
+    uint32_t magic, version, algo;
+    int32_t H, W, A, B, reserved;
+    int64_t frames;
+    uint64_t seed;
+    uint8_t pad[16];
+};
+static_assert(sizeof(StateHeader) == kHeaderBytes, "state header is 64 bytes");
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct fgs_model {
+    fgs_algo algo;
+    int32_t H, W, npix;
+    fgs_gmm_params gp;
+    fgs_pbas_params pp;
+    GmmConsts gc;
+    PbasConsts pc;
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    uint8_t* dev;      // one allocation: state + scratch planes + mask
+    size_t dev_bytes;
+    float4* gmm_state;
+    PbasPlanes pb;
+    uint8_t* mask;
+    // host-frame staging (allocated on the first host push)
+    uint8_t* host_stage;
+    uint8_t* dev_in;
+    hipEvent_t stage_done;
+    bool stage_busy;
+    int64_t t;          // frames pushed
+    bool pending;       // PBAS: intents of frame t-1 not yet applied
+    bool poisoned;
+};
+
+namespace {
+
+fgs_status device_fail(fgs_model* m, hipError_t e, const char* what) {
+    if (m) m->poisoned = true;
+    return fail(FGS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define FGS_HIP(m, call)                                         \
+    do {                                                         \
+        hipError_t e_ = (call);                                  \
+        if (e_ != hipSuccess) return device_fail((m), e_, #call); \
+    } while (0)
+
+size_t gmm_payload_bytes(const fgs_model* m) {
+    return (size_t)(5 * m->gp.Kc + 3 * m->gp.Kd) * (size_t)m->npix * 4;
+}
+size_t pbas_payload_bytes(const fgs_model* m) {
+    const size_t n = (size_t)m->npix;
+    return 2 * (size_t)m->pp.N * n * 4 + 8 * n * 4 + 4 * n * 2;
+}
+size_t payload_bytes(const fgs_model* m) {
+    return m->algo == FGS_GMM ? gmm_payload_bytes(m) : pbas_payload_bytes(m);
+}
+
+fgs_status check_gmm(const fgs_gmm_params& p) {
+    if (p.struct_size != sizeof(fgs_gmm_params))
+        return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u != %zu", p.struct_size,
+                    sizeof(fgs_gmm_params));
+    if (!gmm_supported(p.Kc, p.Kd))
+        return fail(FGS_ERR_INVALID_ARG, "unsupported (Kc, Kd) = (%d, %d)", p.Kc, p.Kd);
+    if (!(p.alpha > 0.f && p.alpha < 1.f) || !(p.lambda > 0.f) || !(p.T_bg > 0.f && p.T_bg < 1.f) ||
+        !(p.w_init > 0.f) || !(p.v_min_c > 0.f) || !(p.v_init_c >= p.v_min_c) ||
+        !(p.v_min_d > 0.f) || !(p.v_init_d >= p.v_min_d) || !(p.w_depth >= 0.f) ||
+        p.depth_max_mm < 1)
+        return fail(FGS_ERR_INVALID_ARG, "GMM parameter out of range");
+    return FGS_OK;
+}
+
+fgs_status check_pbas(const fgs_pbas_params& p) {
+    if (p.struct_size != sizeof(fgs_pbas_params))
+        return fail(FGS_ERR_INVALID_ARG, "fgs_pbas_params.struct_size %u != %zu", p.struct_size,
+                    sizeof(fgs_pbas_params));
+    if (p.N < 2 || p.N > 64) return fail(FGS_ERR_INVALID_ARG, "PBAS N = %d not in [2, 64]", p.N);
+    if (p.min_matches < 1 || p.min_matches > p.N)
+        return fail(FGS_ERR_INVALID_ARG, "min_matches = %d not in [1, N]", p.min_matches);
+    if (!(p.T_lower > 0.f) || !(p.T_upper >= p.T_lower) || !(p.R_scale > 0.f) ||
+        !(p.R_incdec >= 0.f && p.R_incdec < 1.f) || !(p.T_inc >= 0.f) || !(p.T_dec >= 0.f) ||
+        p.depth_max_mm < 1)
+        return fail(FGS_ERR_INVALID_ARG, "PBAS parameter out of range");
+    for (int j = 0; j < 4; ++j)
+        if (!(p.R_lower[j] > 0.f)) return fail(FGS_ERR_INVALID_ARG, "R_lower[%d] must be > 0", j);
+    return FGS_OK;
+}
+
+fgs_status ensure_staging(fgs_model* m) {
+    if (m->host_stage) return FGS_OK;
+    const size_t bytes = align256((size_t)m->npix * 3) + align256((size_t)m->npix * 2);
+    hipError_t e = hipHostMalloc((void**)&m->host_stage, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        m->host_stage = nullptr;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "pinned staging of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    e = hipMalloc((void**)&m->dev_in, bytes);
+    if (e != hipSuccess) {
+        (void)hipHostFree(m->host_stage);
+        m->host_stage = nullptr;
+        m->dev_in = nullptr;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "device input staging of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    FGS_HIP(m, hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
+    m->stage_busy = false;
+    return FGS_OK;
+}
+
+fgs_status flush_pending(fgs_model* m) {
+    if (m->algo != FGS_PBAS || !m->pending) return FGS_OK;
+    FGS_HIP(m, pbas_launch_flush(m->pb, m->H, m->W, (uint32_t)(m->t - 1), m->pp.N, m->stream));
+    m->pending = false;
+    return FGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fgs_abi_version(void) { return FGS_ABI_VERSION; }
+
+const char* fgs_status_str(fgs_status s) {
+    switch (s) {
+        case FGS_OK: return "ok";
+        case FGS_ERR_INVALID_ARG: return "invalid argument";
+        case FGS_ERR_OUT_OF_MEMORY: return "out of memory";
+        case FGS_ERR_DEVICE: return "device error";
+        case FGS_ERR_BAD_STATE: return "bad state";
+        case FGS_ERR_BUSY: return "busy";
+        case FGS_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* fgs_last_error(void) { return g_last_error.c_str(); }
+
+fgs_status fgs_gmm_params_default(fgs_gmm_params* p) {
+    if (!p) return fail(FGS_ERR_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof *p;
+    p->Kc = 3;
+    p->Kd = 3;
+    p->alpha = 0.01f;
+    p->lambda = 2.5f;
+    p->T_bg = 0.7f;
+    p->w_init = 0.05f;
+    p->v_init_c = 675.0f;
+    p->v_min_c = 12.0f;
+    p->v_init_d = 25.0f;
+    p->v_min_d = 1.0f;
+    p->w_depth = 1.0f;
+    p->depth_max_mm = 10000;
+    return FGS_OK;
+}
+
+fgs_status fgs_pbas_params_default(fgs_pbas_params* p) {
+    if (!p) return fail(FGS_ERR_INVALID_ARG, "params is NULL");
+    std::memset(p, 0, sizeof *p);
+    p->struct_size = sizeof *p;
+    p->N = 20;
+    p->min_matches = 2;
+    p->R_incdec = 0.05f;
+    p->R_scale = 5.0f;
+    p->T_inc = 1.0f;
+    p->T_dec = 0.05f;
+    p->T_lower = 2.0f;
+    p->T_upper = 200.0f;
+    p->R_lower[0] = p->R_lower[1] = p->R_lower[2] = 18.0f;
+    p->R_lower[3] = 4.0f;
+    p->depth_max_mm = 10000;
+    p->seed = 0x200200250ull;
+    return FGS_OK;
+}
+
+fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, void* hip_stream,
+                      fgs_model** out) {
+    if (!out) return fail(FGS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (algo != FGS_GMM && algo != FGS_PBAS) return fail(FGS_ERR_INVALID_ARG, "unknown algo %d", (int)algo);
+    if (H < 1 || W < 1 || (int64_t)H * W > kMaxPixels)
+        return fail(FGS_ERR_INVALID_ARG, "bad frame size %d x %d", H, W);
+
+    fgs_model* m = new (std::nothrow) fgs_model();
+    if (!m) return fail(FGS_ERR_OUT_OF_MEMORY, "host allocation");
+    m->algo = algo;
+    m->H = H;
+    m->W = W;
+    m->npix = H * W;
+    fgs_gmm_params_default(&m->gp);
+    fgs_pbas_params_default(&m->pp);
+    fgs_status st = FGS_OK;
+    if (algo == FGS_GMM) {
+        if (params) std::memcpy(&m->gp, params, sizeof m->gp);
+        st = check_gmm(m->gp);
+    } else {
+        if (params) std::memcpy(&m->pp, params, sizeof m->pp);
+        st = check_pbas(m->pp);
+    }
+    if (st != FGS_OK) {
+        delete m;
+        return st;
+    }
+    m->gc = GmmConsts{m->gp.alpha, m->gp.lambda, m->gp.T_bg, m->gp.w_init, m->gp.v_init_c,
+                      m->gp.v_min_c, m->gp.v_init_d, m->gp.v_min_d, m->gp.w_depth,
+                      (uint32_t)m->gp.depth_max_mm};
+    m->pc.N = m->pp.N;
+    m->pc.min_matches = m->pp.min_matches;
+    m->pc.R_incdec = m->pp.R_incdec;
+    m->pc.R_scale = m->pp.R_scale;
+    m->pc.T_inc = m->pp.T_inc;
+    m->pc.T_dec = m->pp.T_dec;
+    m->pc.T_lower = m->pp.T_lower;
+    m->pc.T_upper = m->pp.T_upper;
+    for (int j = 0; j < 4; ++j) m->pc.R_lower[j] = m->pp.R_lower[j];
+    m->pc.depth_max_mm = (uint32_t)m->pp.depth_max_mm;
+    m->pc.key0 = (uint32_t)(m->pp.seed & 0xFFFFFFFFu);
+    m->pc.key1 = (uint32_t)(m->pp.seed >> 32);
+
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) {
+        delete m;
+        return fail(FGS_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    if (hip_stream) {
+        m->stream = (hipStream_t)hip_stream;
+        m->own_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete m;
+            return fail(FGS_ERR_DEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
+        }
+        m->own_stream = true;
+    }
+
+    const size_t n = (size_t)m->npix;
+    size_t off = 0;
+    size_t o_state = 0, o_samples = 0, o_dhist = 0, o_R = 0, o_T = 0, o_S = 0, o_last = 0, o_i0 = 0,
+           o_i1 = 0, o_mask = 0;
+    if (algo == FGS_GMM) {
+        o_state = off;
+        off += align256((size_t)gmm_planes(m->gp.Kc, m->gp.Kd) * n * 16);
+    } else {
+        const size_t N = (size_t)m->pp.N;
+        o_samples = off; off += align256(N * n * 4);
+        o_dhist = off;   off += align256(N * n * 4);
+        o_R = off;       off += align256(n * 16);
+        o_T = off;       off += align256(n * 16);
+        o_S = off;       off += align256(n * 8);
+        o_last = off;    off += align256(n * 4);
+        o_i0 = off;      off += align256(n * 8);
+        o_i1 = off;      off += align256(n * 8);
+    }
+    o_mask = off;
+    off += align256(n);
+    m->dev_bytes = off;
+    e = hipMalloc((void**)&m->dev, off);
+    if (e != hipSuccess) {
+        if (m->own_stream) (void)hipStreamDestroy(m->stream);
+        delete m;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes: %s", off, hipGetErrorString(e));
+    }
+    m->mask = m->dev + o_mask;
+    if (algo == FGS_GMM) {
+        m->gmm_state = reinterpret_cast<float4*>(m->dev + o_state);
+        e = gmm_launch_init(m->gmm_state, m->gp.Kc, m->gp.Kd, m->npix, m->gc, m->stream);
+    } else {
+        m->pb.samples = reinterpret_cast<uint32_t*>(m->dev + o_samples);
+        m->pb.dhist = reinterpret_cast<uint32_t*>(m->dev + o_dhist);
+        m->pb.R = reinterpret_cast<float4*>(m->dev + o_R);
+        m->pb.T = reinterpret_cast<float4*>(m->dev + o_T);
+        m->pb.S = reinterpret_cast<uint2*>(m->dev + o_S);
+        m->pb.last = reinterpret_cast<uint32_t*>(m->dev + o_last);
+        m->pb.intents[0] = reinterpret_cast<uint64_t*>(m->dev + o_i0);
+        m->pb.intents[1] = reinterpret_cast<uint64_t*>(m->dev + o_i1);
+        m->pb.mask = m->mask;
+        e = hipMemsetAsync(m->dev, 0, off, m->stream);
+        if (e == hipSuccess) e = pbas_launch_init_state(m->pb, m->npix, m->pc, m->stream);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(m->mask, 0, n, m->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(m->dev);
+        if (m->own_stream) (void)hipStreamDestroy(m->stream);
+        delete m;
+        return fail(FGS_ERR_DEVICE, "model initialisation: %s", hipGetErrorString(e));
+    }
+    *out = m;
+    return FGS_OK;
+}
+
+fgs_status fgs_destroy(fgs_model* m) {
+    if (!m) return FGS_OK;
+    (void)hipStreamSynchronize(m->stream);
+    if (m->dev) (void)hipFree(m->dev);
+    if (m->dev_in) (void)hipFree(m->dev_in);
+    if (m->host_stage) {
+        (void)hipEventDestroy(m->stage_done);
+        (void)hipHostFree(m->host_stage);
+    }
+    if (m->own_stream) (void)hipStreamDestroy(m->stream);
+    delete m;
+    return FGS_OK;
+}
+
+fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
+                          const uint16_t* depth, int64_t depth_stride, fgs_mem where) {
+    if (!m) return fail(FGS_ERR_INVALID_ARG, "model is NULL");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    if (!rgb || !depth) return fail(FGS_ERR_INVALID_ARG, "frame pointer is NULL");
+    if (rgb_stride < 3 * (int64_t)m->W || depth_stride < 2 * (int64_t)m->W || (depth_stride & 1) ||
+        ((uintptr_t)depth & 1))
+        return fail(FGS_ERR_INVALID_ARG, "bad stride (rgb %lld, depth %lld) for W = %d",
+                    (long long)rgb_stride, (long long)depth_stride, m->W);
+    if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
+        return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    if (m->t >= 0xFFFFFFFFll) return fail(FGS_ERR_BAD_STATE, "frame counter exhausted");
+
+    const uint8_t* drgb = rgb;
+    const uint8_t* ddep = reinterpret_cast<const uint8_t*>(depth);
+    int64_t rs = rgb_stride, ds = depth_stride;
+    if (where == FGS_MEM_HOST) {
+        fgs_status st = ensure_staging(m);
+        if (st != FGS_OK) return st;
+        if (m->stage_busy) FGS_HIP(m, hipEventSynchronize(m->stage_done));
+        const size_t rgb_bytes = (size_t)m->npix * 3;
+        uint8_t* hr = m->host_stage;
+        uint8_t* hd = m->host_stage + align256(rgb_bytes);
+        for (int y = 0; y < m->H; ++y) {
+            std::memcpy(hr + (size_t)y * 3 * m->W, rgb + (size_t)y * rgb_stride, (size_t)3 * m->W);
+            std::memcpy(hd + (size_t)y * 2 * m->W, reinterpret_cast<const uint8_t*>(depth) + (size_t)y * depth_stride,
+                        (size_t)2 * m->W);
+        }
+        const size_t bytes = align256(rgb_bytes) + (size_t)m->npix * 2;
+        FGS_HIP(m, hipMemcpyAsync(m->dev_in, m->host_stage, bytes, hipMemcpyHostToDevice, m->stream));
+        FGS_HIP(m, hipEventRecord(m->stage_done, m->stream));
+        m->stage_busy = true;
+        drgb = m->dev_in;
+        ddep = m->dev_in + align256(rgb_bytes);
+        rs = 3 * (int64_t)m->W;
+        ds = 2 * (int64_t)m->W;
+    }
+
+    if (m->algo == FGS_GMM) {
+        GmmStepArgs a;
+        a.state = m->gmm_state;
+        a.mask = m->mask;
+        a.rgb = drgb;
+        a.depth = ddep;
+        a.rgb_stride = rs;
+        a.depth_stride = ds;
+        a.H = m->H;
+        a.W = m->W;
+        a.npix = m->npix;
+        a.c = m->gc;
+        FGS_HIP(m, gmm_launch_step(a, m->gp.Kc, m->gp.Kd, m->stream));
+    } else {
+        PbasStepArgs a;
+        a.m = m->pb;
+        a.rgb = drgb;
+        a.depth = ddep;
+        a.rgb_stride = rs;
+        a.depth_stride = ds;
+        a.H = m->H;
+        a.W = m->W;
+        a.npix = m->npix;
+        a.t = (uint32_t)m->t;
+        a.apply_pending = m->pending ? 1 : 0;
+        a.c = m->pc;
+        FGS_HIP(m, pbas_launch_step(a, m->stream));
+        m->pending = m->t >= m->pp.N;
+    }
+    m->t += 1;
+    return FGS_OK;
+}
+
+fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem where) {
+    if (!m || !mask) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    if (stride < m->W) return fail(FGS_ERR_INVALID_ARG, "mask stride %lld < W", (long long)stride);
+    if (m->t == 0) return fail(FGS_ERR_BAD_STATE, "no frame has been pushed");
+    if (where == FGS_MEM_HOST) {
+        FGS_HIP(m, hipMemcpy2DAsync(mask, (size_t)stride, m->mask, (size_t)m->W, (size_t)m->W,
+                                    (size_t)m->H, hipMemcpyDeviceToHost, m->stream));
+        FGS_HIP(m, hipStreamSynchronize(m->stream));
+    } else if (where == FGS_MEM_DEVICE) {
+        FGS_HIP(m, hipMemcpy2DAsync(mask, (size_t)stride, m->mask, (size_t)m->W, (size_t)m->W,
+                                    (size_t)m->H, hipMemcpyDeviceToDevice, m->stream));
+    } else {
+        return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    }
+    return FGS_OK;
+}
+
+fgs_status fgs_mask_device_ptr(fgs_model* m, const uint8_t** out) {
+    if (!m || !out) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    *out = m->mask;
+    return FGS_OK;
+}
+
+fgs_status fgs_state_size(const fgs_model* m, size_t* bytes) {
+    if (!m || !bytes) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    *bytes = kHeaderBytes + payload_bytes(m);
+    return FGS_OK;
+}
+
+fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) {
+    if (!m || !dst) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    const size_t payload = payload_bytes(m);
+    if (bytes != kHeaderBytes + payload)
+        return fail(FGS_ERR_INVALID_ARG, "state buffer is %zu bytes, need %zu", bytes, kHeaderBytes + payload);
+    if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
+        return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    fgs_status st = flush_pending(m);
+    if (st != FGS_OK) return st;
+
+    StateHeader h;
+    std::memset(&h, 0, sizeof h);
+    h.magic = kStateMagic;
+    h.version = kStateVersion;
+    h.algo = (uint32_t)m->algo;
+    h.H = m->H;
+    h.W = m->W;
+    h.A = m->algo == FGS_GMM ? m->gp.Kc : m->pp.N;
+    h.B = m->algo == FGS_GMM ? m->gp.Kd : 0;
+    h.frames = m->t;
+    h.seed = m->algo == FGS_PBAS ? m->pp.seed : 0;
+
+    uint8_t* tmp = nullptr;
+    uint8_t* target = reinterpret_cast<uint8_t*>(dst) + kHeaderBytes;
+    if (where == FGS_MEM_HOST) {
+        FGS_HIP(m, hipMalloc((void**)&tmp, payload));
+        target = tmp;
+    }
+    hipError_t e = m->algo == FGS_GMM
+                       ? gmm_launch_export(m->gmm_state, reinterpret_cast<float*>(target), m->gp.Kc,
+                                           m->gp.Kd, m->npix, m->stream)
+                       : pbas_launch_export(m->pb, m->npix, m->pp.N, target, m->stream);
+    if (e == hipSuccess) {
+        if (where == FGS_MEM_HOST) {
+            std::memcpy(dst, &h, sizeof h);
+            e = hipMemcpyAsync(reinterpret_cast<uint8_t*>(dst) + kHeaderBytes, tmp, payload,
+                               hipMemcpyDeviceToHost, m->stream);
+        } else {
+            e = hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, m->stream);
+        }
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return device_fail(m, e, "copy_state");
+    return FGS_OK;
+}
+
+fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem where) {
+    if (!m || !src) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    const size_t payload = payload_bytes(m);
+    if (bytes != kHeaderBytes + payload)
+        return fail(FGS_ERR_INVALID_ARG, "state blob is %zu bytes, need %zu", bytes, kHeaderBytes + payload);
+    if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
+        return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    StateHeader h;
+    if (where == FGS_MEM_HOST) {
+        std::memcpy(&h, src, sizeof h);
+    } else {
+        FGS_HIP(m, hipMemcpyAsync(&h, src, sizeof h, hipMemcpyDeviceToHost, m->stream));
+        FGS_HIP(m, hipStreamSynchronize(m->stream));
+    }
+    const int A = m->algo == FGS_GMM ? m->gp.Kc : m->pp.N;
+    const int B = m->algo == FGS_GMM ? m->gp.Kd : 0;
+    if (h.magic != kStateMagic || h.version != kStateVersion || h.algo != (uint32_t)m->algo ||
+        h.H != m->H || h.W != m->W || h.A != A || h.B != B || h.frames < 0 || h.frames >= 0xFFFFFFFFll)
+        return fail(FGS_ERR_INVALID_ARG, "state header does not match this model");
+    if (m->algo == FGS_PBAS && h.seed != m->pp.seed)
+        return fail(FGS_ERR_INVALID_ARG, "state was taken with another PBAS seed");
+
+    uint8_t* tmp = nullptr;
+    const uint8_t* srcp = reinterpret_cast<const uint8_t*>(src) + kHeaderBytes;
+    hipError_t e = hipSuccess;
+    if (where == FGS_MEM_HOST) {
+        FGS_HIP(m, hipMalloc((void**)&tmp, payload));
+        e = hipMemcpyAsync(tmp, srcp, payload, hipMemcpyHostToDevice, m->stream);
+        srcp = tmp;
+    }
+    if (e == hipSuccess)
+        e = m->algo == FGS_GMM ? gmm_launch_import(m->gmm_state, reinterpret_cast<const float*>(srcp),
+                                                   m->gp.Kc, m->gp.Kd, m->npix, m->stream)
+                               : pbas_launch_import(m->pb, m->npix, m->pp.N, srcp, m->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (tmp) (void)hipFree(tmp);
+    if (e != hipSuccess) return device_fail(m, e, "set_state");
+    m->t = h.frames;
+    m->pending = false;
+    return FGS_OK;
+}
+
+fgs_status fgs_frame_index(const fgs_model* m, int64_t* t) {
+    if (!m || !t) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    *t = m->t;
+    return FGS_OK;
+}
+
+fgs_status fgs_sync(fgs_model* m) {
+    if (!m) return fail(FGS_ERR_INVALID_ARG, "model is NULL");
+    FGS_HIP(m, hipStreamSynchronize(m->stream));
+    return FGS_OK;
+}
+
+fgs_status fgs_stream(const fgs_model* m, void** hip_stream) {
+    if (!m || !hip_stream) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    *hip_stream = (void*)m->stream;
+    return FGS_OK;
+}
+
+fgs_status fgs_device_bytes(const fgs_model* m, size_t* bytes) {
+    if (!m || !bytes) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    size_t b = m->dev_bytes;
+    if (m->dev_in) b += align256((size_t)m->npix * 3) + align256((size_t)m->npix * 2);
+    *bytes = b;
+    return FGS_OK;
+}
+
+fgs_status fgs_philox4x32_10(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
+                             void* hip_stream) {
+    if (n < 0 || (n > 0 && (!ctr || !out))) return fail(FGS_ERR_INVALID_ARG, "bad philox arguments");
+    if (((uintptr_t)ctr & 15) || ((uintptr_t)out & 15))
+        return fail(FGS_ERR_INVALID_ARG, "philox buffers must be 16-byte aligned");
+    hipError_t e = diag_launch_philox(seed, ctr, out, n, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "philox kernel: %s", hipGetErrorString(e));
+    return FGS_OK;
+}
+
+fgs_status fgs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
+    if (!src || !dst || (bytes & 15) || ((uintptr_t)src & 15) || ((uintptr_t)dst & 15))
+        return fail(FGS_ERR_INVALID_ARG, "copy probe needs 16-byte aligned buffers and size");
+    hipError_t e = diag_launch_copy(src, dst, bytes, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "copy kernel: %s", hipGetErrorString(e));
+    return FGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,331 @@
+"""ctypes binding of libfgs (include/fgs.h): same names, argument marshalling only.
+
+Every step of the classify-and-update path runs in the library's HIP kernels.
+There is no fallback: if libfgs.so is missing or fails to load, every call
+raises.  PyTorch is used only for device memory and streams (``Model`` accepts
+torch tensors and ``torch.cuda.Stream``s).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_int32, c_int64, c_size_t, c_uint32, c_uint64, c_void_p
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfgs.so")
+
+FGS_OK = 0
+FGS_ERR_INVALID_ARG = 1
+FGS_ERR_OUT_OF_MEMORY = 2
+FGS_ERR_DEVICE = 3
+FGS_ERR_BAD_STATE = 4
+FGS_ERR_BUSY = 5
+FGS_ERR_UNSUPPORTED = 6
+
+FGS_GMM = 1
+FGS_PBAS = 2
+FGS_MEM_HOST = 0
+FGS_MEM_DEVICE = 1
+STATE_HEADER_BYTES = 64
+
+
+class FgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fgs status {status}: {msg}")
+        self.status = status
+
+
+class fgs_gmm_params(ctypes.Structure):
+    _fields_ = [("struct_size", c_uint32), ("Kc", c_int32), ("Kd", c_int32),
+                ("alpha", ctypes.c_float), ("lambda_", ctypes.c_float), ("T_bg", ctypes.c_float),
+                ("w_init", ctypes.c_float), ("v_init_c", ctypes.c_float), ("v_min_c", ctypes.c_float),
+                ("v_init_d", ctypes.c_float), ("v_min_d", ctypes.c_float), ("w_depth", ctypes.c_float),
+                ("depth_max_mm", c_int32)]
+
+
+class fgs_pbas_params(ctypes.Structure):
+    _fields_ = [("struct_size", c_uint32), ("N", c_int32), ("min_matches", c_int32),
+                ("R_incdec", ctypes.c_float), ("R_scale", ctypes.c_float),
+                ("T_inc", ctypes.c_float), ("T_dec", ctypes.c_float),
+                ("T_lower", ctypes.c_float), ("T_upper", ctypes.c_float),
+                ("R_lower", ctypes.c_float * 4), ("depth_max_mm", c_int32), ("reserved0", c_int32),
+                ("seed", c_uint64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FgsError(-1, f"{LIB_PATH} is not built (run python -m paper_2002_00250_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    S = c_int32
+    sig = {
+        "fgs_abi_version": (c_int32, []),
+        "fgs_status_str": (c_char_p, [c_int32]),
+        "fgs_last_error": (c_char_p, []),
+        "fgs_gmm_params_default": (S, [POINTER(fgs_gmm_params)]),
+        "fgs_pbas_params_default": (S, [POINTER(fgs_pbas_params)]),
+        "fgs_create": (S, [c_int32, c_int32, c_int32, c_void_p, c_void_p, POINTER(c_void_p)]),
+        "fgs_destroy": (S, [c_void_p]),
+        "fgs_push_frame": (S, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32]),
+        "fgs_get_mask": (S, [c_void_p, c_void_p, c_int64, c_int32]),
+        "fgs_mask_device_ptr": (S, [c_void_p, POINTER(c_void_p)]),
+        "fgs_state_size": (S, [c_void_p, POINTER(c_size_t)]),
+        "fgs_copy_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
+        "fgs_set_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
+        "fgs_frame_index": (S, [c_void_p, POINTER(c_int64)]),
+        "fgs_sync": (S, [c_void_p]),
+        "fgs_stream": (S, [c_void_p, POINTER(c_void_p)]),
+        "fgs_device_bytes": (S, [c_void_p, POINTER(c_size_t)]),
+        "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
+        "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def lib():
+    return _load()
+
+
+def _check(status: int):
+    if status != FGS_OK:
+        msg = _load().fgs_last_error().decode(errors="replace")
+        raise FgsError(status, msg)
+
+
+# ---------------------------------------------------------------- C entry points
+def fgs_abi_version() -> int:
+    return _load().fgs_abi_version()
+
+
+def fgs_status_str(s: int) -> str:
+    return _load().fgs_status_str(s).decode()
+
+
+def fgs_last_error() -> str:
+    return _load().fgs_last_error().decode(errors="replace")
+
+
+def fgs_gmm_params_default() -> fgs_gmm_params:
+    p = fgs_gmm_params()
+    _check(_load().fgs_gmm_params_default(byref(p)))
+    return p
+
+
+def fgs_pbas_params_default() -> fgs_pbas_params:
+    p = fgs_pbas_params()
+    _check(_load().fgs_pbas_params_default(byref(p)))
+    return p
+
+
+def fgs_create(algo: int, H: int, W: int, params=None, hip_stream: int | None = None) -> int:
+    out = c_void_p()
+    pp = byref(params) if params is not None else None
+    _check(_load().fgs_create(algo, H, W, pp, c_void_p(hip_stream or 0), byref(out)))
+    return out.value
+
+
+def fgs_destroy(m: int) -> None:
+    _check(_load().fgs_destroy(c_void_p(m)))
+
+
+def fgs_push_frame(m: int, rgb: int, rgb_stride: int, depth: int, depth_stride: int, where: int) -> None:
+    _check(_load().fgs_push_frame(c_void_p(m), c_void_p(rgb), rgb_stride, c_void_p(depth),
+                                  depth_stride, where))
+
+
+def fgs_get_mask(m: int, mask: int, stride: int, where: int) -> None:
+    _check(_load().fgs_get_mask(c_void_p(m), c_void_p(mask), stride, where))
+
+
+def fgs_mask_device_ptr(m: int) -> int:
+    out = c_void_p()
+    _check(_load().fgs_mask_device_ptr(c_void_p(m), byref(out)))
+    return out.value
+
+
+def fgs_state_size(m: int) -> int:
+    out = c_size_t()
+    _check(_load().fgs_state_size(c_void_p(m), byref(out)))
+    return out.value
+
+
+def fgs_copy_state(m: int, dst: int, nbytes: int, where: int) -> None:
+    _check(_load().fgs_copy_state(c_void_p(m), c_void_p(dst), nbytes, where))
+
+
+def fgs_set_state(m: int, src: int, nbytes: int, where: int) -> None:
+    _check(_load().fgs_set_state(c_void_p(m), c_void_p(src), nbytes, where))
+
+
+def fgs_frame_index(m: int) -> int:
+    out = c_int64()
+    _check(_load().fgs_frame_index(c_void_p(m), byref(out)))
+    return out.value
+
+
+def fgs_sync(m: int) -> None:
+    _check(_load().fgs_sync(c_void_p(m)))
+
+
+def fgs_stream(m: int) -> int:
+    out = c_void_p()
+    _check(_load().fgs_stream(c_void_p(m), byref(out)))
+    return out.value or 0
+
+
+def fgs_device_bytes(m: int) -> int:
+    out = c_size_t()
+    _check(_load().fgs_device_bytes(c_void_p(m), byref(out)))
+    return out.value
+
+
+def fgs_philox4x32_10(seed: int, ctr: int, out: int, n: int, hip_stream: int | None = None) -> None:
+    _check(_load().fgs_philox4x32_10(seed, c_void_p(ctr), c_void_p(out), n, c_void_p(hip_stream or 0)))
+
+
+def fgs_copy_probe(src: int, dst: int, nbytes: int, hip_stream: int | None = None) -> None:
+    _check(_load().fgs_copy_probe(c_void_p(src), c_void_p(dst), nbytes, c_void_p(hip_stream or 0)))
+
+
+# ---------------------------------------------------------------- state layout
+def unpack_state(blob: np.ndarray) -> dict:
+    """Split a serialised state (see fgs_copy_state) into named numpy planes."""
+    b = np.ascontiguousarray(blob).view(np.uint8)
+    hdr = b[:STATE_HEADER_BYTES]
+    magic, version, algo = (int(v) for v in hdr[:12].view(np.uint32))
+    H, W, A, B = (int(v) for v in hdr[12:28].view(np.int32))
+    frames = int(hdr[32:40].view(np.int64)[0])
+    seed = int(hdr[40:48].view(np.uint64)[0])
+    if magic != 0x53534746:
+        raise ValueError("not an fgs state blob")
+    pay = b[STATE_HEADER_BYTES:]
+    n = H * W
+    out = dict(algo=algo, H=H, W=W, t=frames, seed=seed)
+    if algo == FGS_GMM:
+        Kc, Kd = A, B
+        f = pay.view(np.float32)
+        o = 0
+
+        def take(k, shape):
+            nonlocal o
+            a = f[o:o + k * n].reshape(shape)
+            o += k * n
+            return a
+        out.update(Kc=Kc, Kd=Kd, w_c=take(Kc, (Kc, H, W)), mu_c=take(3 * Kc, (Kc, 3, H, W)),
+                   v_c=take(Kc, (Kc, H, W)), w_d=take(Kd, (Kd, H, W)), mu_d=take(Kd, (Kd, H, W)),
+                   v_d=take(Kd, (Kd, H, W)))
+    else:
+        N = A
+        u32 = pay[:2 * N * n * 4].view(np.uint32)
+        out.update(N=N, samples=u32[:N * n].reshape(N, H, W), dhist=u32[N * n:].reshape(N, H, W))
+        rt = pay[2 * N * n * 4:2 * N * n * 4 + 8 * n * 4].view(np.float32)
+        out.update(R=rt[:4 * n].reshape(4, H, W), T=rt[4 * n:].reshape(4, H, W))
+        out.update(S=pay[2 * N * n * 4 + 8 * n * 4:].view(np.uint16).reshape(4, H, W))
+    return out
+
+
+def pack_state(st: dict) -> np.ndarray:
+    """Inverse of unpack_state for a dict with the same keys."""
+    hdr = np.zeros(STATE_HEADER_BYTES, np.uint8)
+    algo = st["algo"]
+    A, B = (st["Kc"], st["Kd"]) if algo == FGS_GMM else (st["N"], 0)
+    hdr[:12] = np.array([0x53534746, 1, algo], np.uint32).view(np.uint8)
+    hdr[12:32] = np.array([st["H"], st["W"], A, B, 0], np.int32).view(np.uint8)
+    hdr[32:40] = np.array([st["t"]], np.int64).view(np.uint8)
+    hdr[40:48] = np.array([st.get("seed", 0)], np.uint64).view(np.uint8)
+    if algo == FGS_GMM:
+        parts = [np.asarray(st[k], np.float32).ravel() for k in ("w_c", "mu_c", "v_c", "w_d", "mu_d", "v_d")]
+    else:
+        parts = [np.asarray(st["samples"], np.uint32).ravel(), np.asarray(st["dhist"], np.uint32).ravel(),
+                 np.asarray(st["R"], np.float32).ravel(), np.asarray(st["T"], np.float32).ravel(),
+                 np.asarray(st["S"], np.uint16).ravel()]
+    return np.concatenate([hdr] + [p.view(np.uint8) for p in parts])
+
+
+# ---------------------------------------------------------------- convenience
+class Model:
+    """A background model on the current GPU.  Frames are torch tensors (device or host)
+    or numpy arrays; ``rgb`` [H, W, 3] uint8, ``depth`` [H, W] uint16 (torch: int16 view
+    or uint16)."""
+
+    def __init__(self, algo: int, H: int, W: int, params=None, stream=None):
+        import torch
+        self._torch = torch
+        self.algo, self.H, self.W = algo, H, W
+        self.params = params
+        handle = stream.cuda_stream if stream is not None else 0
+        self.handle = fgs_create(algo, H, W, params, handle)
+        self._mask_ptr = fgs_mask_device_ptr(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            fgs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptr_where(x):
+        if isinstance(x, np.ndarray):
+            return x.ctypes.data, FGS_MEM_HOST
+        return x.data_ptr(), (FGS_MEM_DEVICE if x.is_cuda else FGS_MEM_HOST)
+
+    def push(self, rgb, depth):
+        if isinstance(rgb, np.ndarray):
+            rgb = np.ascontiguousarray(rgb, np.uint8)
+            depth = np.ascontiguousarray(depth, np.uint16)
+        pr, wr = self._ptr_where(rgb)
+        pd, wd = self._ptr_where(depth)
+        if wr != wd:
+            raise ValueError("rgb and depth must both be host or both be device memory")
+        fgs_push_frame(self.handle, pr, rgb.stride(0) if not isinstance(rgb, np.ndarray) else rgb.strides[0],
+                       pd, (depth.stride(0) * 2) if not isinstance(depth, np.ndarray) else depth.strides[0], wr)
+
+    def mask_host(self) -> np.ndarray:
+        out = np.empty((self.H, self.W), np.uint8)
+        fgs_get_mask(self.handle, out.ctypes.data, self.W, FGS_MEM_HOST)
+        return out
+
+    def mask_into(self, out) -> None:
+        """Device-to-device copy of the latest mask into a uint8 [H, W] cuda tensor."""
+        fgs_get_mask(self.handle, out.data_ptr(), out.stride(0), FGS_MEM_DEVICE)
+
+    def state_blob(self) -> np.ndarray:
+        n = fgs_state_size(self.handle)
+        out = np.empty(n, np.uint8)
+        fgs_copy_state(self.handle, out.ctypes.data, n, FGS_MEM_HOST)
+        return out
+
+    def state(self) -> dict:
+        return unpack_state(self.state_blob())
+
+    def set_state(self, st) -> None:
+        blob = st if isinstance(st, np.ndarray) else pack_state(st)
+        blob = np.ascontiguousarray(blob, np.uint8)
+        fgs_set_state(self.handle, blob.ctypes.data, blob.size, FGS_MEM_HOST)
+
+    @property
+    def t(self) -> int:
+        return fgs_frame_index(self.handle)
+
+    def sync(self):
+        fgs_sync(self.handle)
+
+    @property
+    def stream_handle(self) -> int:
+        return fgs_stream(self.handle)

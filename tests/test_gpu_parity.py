@@ -1,0 +1,344 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same seeded
+inputs.  Bar: masks may differ on at most 0.01 % of pixel-frames and float state within
+1e-4 relative (|a-b| <= 1e-4 max(|a|,|b|) + 1e-7); PBAS integer state exact.  Both
+sides round every operation the same way, so the expected result is bit-exact and the
+actual counts are printed."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_util import compare_gmm_state, compare_pbas_state, log, to_dev  # noqa: E402
+from oracle.gmm import GmmParams, GmmRef  # noqa: E402
+from oracle.pbas import PbasParams, PbasRef  # noqa: E402
+from synth import Scene, preset  # noqa: E402
+
+MASK_TOL = 1e-4   # fraction of pixel-frames
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_00250_amd import fgs
+    fgs.lib()           # fails loudly if libfgs.so is not built
+    yield
+
+
+def _gmm_params_c(p: GmmParams):
+    from paper_2002_00250_amd import fgs
+    c = fgs.fgs_gmm_params_default()
+    c.Kc, c.Kd = p.Kc, p.Kd
+    c.alpha, c.lambda_, c.T_bg, c.w_init = p.alpha, p.lam, p.T_bg, p.w_init
+    c.v_init_c, c.v_min_c, c.v_init_d, c.v_min_d = p.v_init_c, p.v_min_c, p.v_init_d, p.v_min_d
+    c.w_depth, c.depth_max_mm = p.w_depth, p.depth_max_mm
+    return c
+
+
+def _pbas_params_c(p: PbasParams):
+    from paper_2002_00250_amd import fgs
+    c = fgs.fgs_pbas_params_default()
+    c.N, c.min_matches = p.N, p.min_matches
+    c.R_incdec, c.R_scale, c.T_inc, c.T_dec = p.R_incdec, p.R_scale, p.T_inc, p.T_dec
+    c.T_lower, c.T_upper = p.T_lower, p.T_upper
+    for j in range(4):
+        c.R_lower[j] = p.R_lower[j]
+    c.depth_max_mm, c.seed = p.depth_max_mm, p.seed
+    return c
+
+
+def _model(algo, H, W, params):
+    from paper_2002_00250_amd import fgs
+    cp = _gmm_params_c(params) if algo == fgs.FGS_GMM else _pbas_params_c(params)
+    return fgs.Model(algo, H, W, cp)
+
+
+# ------------------------------------------------------------------ Philox
+def test_philox_words_match_oracle():
+    from paper_2002_00250_amd import fgs
+    from oracle.philox import philox4x32_10
+    n = 1 << 20
+    rng = np.random.default_rng(1)
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4096, 1:] = 0
+    ctr[:4096, 0] = np.arange(4096)
+    seed = 0x0123456789ABCDEF
+    dc = torch.from_numpy(ctr.view(np.int32)).cuda()
+    out = torch.zeros_like(dc)
+    fgs.fgs_philox4x32_10(seed, dc.data_ptr(), out.data_ptr(), n, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    exp = np.stack(philox4x32_10(ctr[:, 0], ctr[:, 1], ctr[:, 2], ctr[:, 3], seed & 0xFFFFFFFF, seed >> 32), -1)
+    bad = int((got != exp).sum())
+    log(f"philox: {n} counters, {bad} words differ")
+    assert bad == 0
+
+
+# ------------------------------------------------------------------ GMM
+def _run_gmm_pair(cfg, p, frames, host_frames=False, strided=False):
+    from paper_2002_00250_amd import fgs
+    sc = Scene(cfg)
+    ref = GmmRef(cfg.H, cfg.W, p)
+    m = _model(fgs.FGS_GMM, cfg.H, cfg.W, p)
+    diff = total = 0
+    for t in range(frames):
+        rgb, D, _ = sc.frame(t)
+        exp = ref.step(rgb, D)
+        if host_frames:
+            m.push(rgb, D)
+        elif strided:
+            pad_r = torch.zeros((cfg.H, 3 * cfg.W + 13), dtype=torch.uint8, device="cuda")
+            pad_d = torch.zeros((cfg.H, cfg.W + 5), dtype=torch.int16, device="cuda")
+            r, d = to_dev(rgb, D)
+            pad_r[:, :3 * cfg.W] = r.reshape(cfg.H, -1)
+            pad_d[:, :cfg.W] = d
+            fgs.fgs_push_frame(m.handle, pad_r.data_ptr(), pad_r.stride(0), pad_d.data_ptr(),
+                               pad_d.stride(0) * 2, fgs.FGS_MEM_DEVICE)
+            torch.cuda.synchronize()
+        else:
+            r, d = to_dev(rgb, D)
+            m.push(r, d)
+        got = m.mask_host()
+        diff += int((got != exp).sum())
+        total += got.size
+    n, bad, neq = compare_gmm_state(m.state(), ref.state_planes())
+    m.close()
+    return diff, total, n, bad, neq
+
+
+def test_gmm_parity_320x240_k3_100_frames():
+    cfg = preset("gmm_320x240")
+    diff, total, n, bad, neq = _run_gmm_pair(cfg, GmmParams(Kc=3, Kd=3), 100)
+    log(f"gmm 320x240 K=3 100 frames: mask diff {diff}/{total}, state bad {bad}/{n}, not bit-equal {neq}")
+    assert diff <= MASK_TOL * total and bad == 0
+
+
+@pytest.mark.parametrize("H,W,Kc,Kd,frames,mode", [
+    (1, 1, 3, 3, 20, "device"),
+    (7, 13, 5, 5, 30, "device"),
+    (33, 257, 7, 3, 25, "device"),
+    (19, 70, 1, 1, 25, "host"),
+    (24, 50, 7, 7, 25, "strided"),
+    (48, 64, 2, 2, 25, "device"),
+    (41, 37, 4, 4, 25, "host"),
+    (40, 40, 6, 6, 25, "device"),
+])
+def test_gmm_parity_edge_shapes(H, W, Kc, Kd, frames, mode):
+    cfg = preset("gmm_320x240", H=H, W=W, n_objects=2)
+    diff, total, n, bad, neq = _run_gmm_pair(cfg, GmmParams(Kc=Kc, Kd=Kd), frames,
+                                             host_frames=mode == "host", strided=mode == "strided")
+    log(f"gmm {H}x{W} K={Kc}/{Kd} {mode}: mask diff {diff}/{total}, state bad {bad}, not bit-equal {neq}")
+    assert diff == 0 and bad == 0
+
+
+def test_gmm_parity_1280x720_k5_sampled_pixels():
+    # Full-size launch (the benchmark configuration); every pixel's recursion is
+    # independent, so the oracle follows a random sample of pixels one by one.
+    from paper_2002_00250_amd import fgs
+    cfg = preset("hd_1280x720")
+    p = GmmParams(Kc=5, Kd=5)
+    sc = Scene(cfg)
+    rng = np.random.default_rng(3)
+    sel = np.sort(rng.choice(cfg.H * cfg.W, 4096, replace=False))
+    ys, xs = sel // cfg.W, sel % cfg.W
+    ref = GmmRef(1, sel.size, p)
+    m = _model(fgs.FGS_GMM, cfg.H, cfg.W, p)
+    diff = total = 0
+    frames = 120
+    for t in range(frames):
+        rgb, D, _ = sc.frame(t)
+        r, d = to_dev(rgb, D)
+        m.push(r, d)
+        exp = ref.step(rgb[ys, xs][None], D[ys, xs][None])[0]
+        got = m.mask_host()[ys, xs]
+        diff += int((got != exp).sum())
+        total += sel.size
+    st = m.state()
+    sub = {k: st[k][..., ys, xs] for k in ("w_c", "mu_c", "v_c", "w_d", "mu_d", "v_d")}
+    refst = {k: v[..., 0, :] for k, v in ref.state_planes().items() if k != "t"}
+    n, bad, neq = compare_gmm_state(sub, refst)
+    log(f"gmm 1280x720 K=5 {frames} frames, {sel.size} sampled px: mask diff {diff}/{total}, "
+        f"state bad {bad}/{n}, not bit-equal {neq}")
+    m.close()
+    assert diff <= MASK_TOL * total and bad == 0
+
+
+def test_gmm_state_round_trip_and_determinism():
+    from paper_2002_00250_amd import fgs
+    cfg = preset("gmm_320x240", H=60, W=90)
+    p = GmmParams(Kc=3, Kd=3)
+    sc = Scene(cfg)
+    frames = [sc.frame(t)[:2] for t in range(30)]
+    a = _model(fgs.FGS_GMM, 60, 90, p)
+    for rgb, D in frames[:15]:
+        a.push(*to_dev(rgb, D))
+    blob = a.state_blob()
+    b = _model(fgs.FGS_GMM, 60, 90, p)
+    b.set_state(blob)
+    assert b.t == 15
+    np.testing.assert_array_equal(b.state_blob(), blob)
+    for rgb, D in frames[15:]:
+        a.push(*to_dev(rgb, D))
+        b.push(*to_dev(rgb, D))
+        np.testing.assert_array_equal(a.mask_host(), b.mask_host())
+    np.testing.assert_array_equal(a.state_blob(), b.state_blob())
+    # oracle continues from the same state
+    ref = GmmRef(60, 90, p)
+    ref.set_state_planes(fgs.unpack_state(blob))
+    for rgb, D in frames[15:]:
+        ref.step(rgb, D)
+    n, bad, neq = compare_gmm_state(a.state(), ref.state_planes())
+    assert bad == 0
+    a.close()
+    b.close()
+
+
+# ------------------------------------------------------------------ PBAS
+def _run_pbas_pair(cfg, p, frames, host_frames=False):
+    from paper_2002_00250_amd import fgs
+    sc = Scene(cfg)
+    ref = PbasRef(cfg.H, cfg.W, p)
+    m = _model(fgs.FGS_PBAS, cfg.H, cfg.W, p)
+    diff = total = 0
+    for t in range(frames):
+        rgb, D, _ = sc.frame(t)
+        exp = ref.step(rgb, D)
+        if host_frames:
+            m.push(rgb, D)
+        else:
+            m.push(*to_dev(rgb, D))
+        got = m.mask_host()
+        diff += int((got != exp).sum())
+        total += got.size
+    res = compare_pbas_state(m.state(), ref.state_planes())
+    m.close()
+    return diff, total, res
+
+
+@pytest.mark.parametrize("H,W,N,frames,mode", [
+    (70, 90, 20, 90, "device"),     # several 64x4 tiles, ragged in x and y
+    (1, 1, 2, 20, "device"),
+    (5, 3, 4, 30, "host"),
+    (9, 130, 8, 40, "device"),
+    (37, 64, 35, 70, "device"),
+])
+def test_pbas_parity_trajectories(H, W, N, frames, mode):
+    cfg = preset("pbas_640x480", H=H, W=W)
+    p = PbasParams(N=N, seed=0xABC + N)
+    diff, total, res = _run_pbas_pair(cfg, p, frames, host_frames=mode == "host")
+    log(f"pbas {H}x{W} N={N} {frames} frames: mask diff {diff}/{total}, state {res}")
+    assert diff <= MASK_TOL * total
+    assert res["samples"] == 0 and res["dhist"] == 0 and res["S"] == 0
+    assert res["R"] == 0 and res["T"] == 0
+
+
+def test_pbas_parity_640x480_n20_prefix_and_transitions():
+    # The 640x480 N=20 workload: the full trajectory over its first 36 frames (20 fill +
+    # 16 updating), then single-frame transitions from the GPU's own state at later frames
+    # of the 300-frame sequence, each checked over the whole image.
+    from paper_2002_00250_amd import fgs
+    cfg = preset("pbas_640x480")
+    p = PbasParams(N=20)
+    sc = Scene(cfg)
+    ref = PbasRef(cfg.H, cfg.W, p)
+    m = _model(fgs.FGS_PBAS, cfg.H, cfg.W, p)
+    diff = total = 0
+    for t in range(36):
+        rgb, D, _ = sc.frame(t)
+        exp = ref.step(rgb, D)
+        m.push(*to_dev(rgb, D))
+        got = m.mask_host()
+        diff += int((got != exp).sum())
+        total += got.size
+    res = compare_pbas_state(m.state(), ref.state_planes())
+    log(f"pbas 640x480 N=20 prefix 36: mask diff {diff}/{total}, state {res}")
+    assert diff <= MASK_TOL * total and all(v == 0 for k, v in res.items() if not k.endswith("bits"))
+    checks = {100, 101, 199, 299}
+    tdiff = ttotal = 0
+    for t in range(36, 300):
+        rgb, D, _ = sc.frame(t)
+        if t in checks:
+            ref.set_state_planes(m.state())
+            exp = ref.step(rgb, D)
+        m.push(*to_dev(rgb, D))
+        if t in checks:
+            got = m.mask_host()
+            tdiff += int((got != exp).sum())
+            ttotal += got.size
+            res = compare_pbas_state(m.state(), ref.state_planes())
+            log(f"pbas 640x480 transition at t={t}: mask diff {int((got != exp).sum())}, state {res}")
+            assert all(v == 0 for k, v in res.items() if not k.endswith("bits"))
+    assert tdiff <= MASK_TOL * ttotal
+    m.close()
+
+
+def test_pbas_parity_1280x720_n35_transitions():
+    from paper_2002_00250_amd import fgs
+    cfg = preset("hd_1280x720")
+    p = PbasParams(N=35)
+    sc = Scene(cfg)
+    ref = PbasRef(cfg.H, cfg.W, p)
+    m = _model(fgs.FGS_PBAS, cfg.H, cfg.W, p)
+    for t in range(80):
+        rgb, D, _ = sc.frame(t)
+        if t in (35, 36, 79):
+            ref.set_state_planes(m.state())
+            exp = ref.step(rgb, D)
+        m.push(*to_dev(rgb, D))
+        if t in (35, 36, 79):
+            got = m.mask_host()
+            res = compare_pbas_state(m.state(), ref.state_planes())
+            log(f"pbas 1280x720 N=35 transition at t={t}: mask diff {int((got != exp).sum())}, state {res}")
+            assert int((got != exp).sum()) <= MASK_TOL * got.size
+            assert all(v == 0 for k, v in res.items() if not k.endswith("bits"))
+    m.close()
+
+
+def test_pbas_state_round_trip_and_determinism():
+    from paper_2002_00250_amd import fgs
+    cfg = preset("pbas_640x480", H=50, W=70)
+    p = PbasParams(N=10)
+    sc = Scene(cfg)
+    frames = [sc.frame(t)[:2] for t in range(40)]
+    a = _model(fgs.FGS_PBAS, 50, 70, p)
+    c = _model(fgs.FGS_PBAS, 50, 70, p)
+    for rgb, D in frames[:25]:
+        a.push(*to_dev(rgb, D))
+        c.push(*to_dev(rgb, D))
+    blob = a.state_blob()           # applies pending neighbour writes
+    b = _model(fgs.FGS_PBAS, 50, 70, p)
+    b.set_state(blob)
+    for rgb, D in frames[25:]:
+        for mdl in (a, b, c):
+            mdl.push(*to_dev(rgb, D))
+        ma, mb, mc = a.mask_host(), b.mask_host(), c.mask_host()
+        np.testing.assert_array_equal(ma, mb)
+        np.testing.assert_array_equal(ma, mc)   # reading the state does not perturb the run
+    np.testing.assert_array_equal(a.state_blob(), b.state_blob())
+    np.testing.assert_array_equal(a.state_blob(), c.state_blob())
+    for mdl in (a, b, c):
+        mdl.close()
+
+
+# ------------------------------------------------------------------ ABI behaviour
+def test_error_paths():
+    from paper_2002_00250_amd import fgs
+    m = fgs.Model(fgs.FGS_GMM, 8, 8)
+    with pytest.raises(fgs.FgsError) as e:
+        m.mask_host()
+    assert e.value.status == fgs.FGS_ERR_BAD_STATE
+    r = torch.zeros((8, 8, 3), dtype=torch.uint8, device="cuda")
+    d = torch.zeros((8, 8), dtype=torch.int16, device="cuda")
+    with pytest.raises(fgs.FgsError) as e:
+        fgs.fgs_push_frame(m.handle, r.data_ptr(), 5, d.data_ptr(), 16, fgs.FGS_MEM_DEVICE)
+    assert e.value.status == fgs.FGS_ERR_INVALID_ARG
+    m.push(r, d)
+    assert m.t == 1 and not m.mask_host().any()
+    with pytest.raises(fgs.FgsError):
+        m.set_state(np.zeros(10, np.uint8))
+    p = fgs.fgs_gmm_params_default()
+    p.Kc, p.Kd = 4, 2
+    with pytest.raises(fgs.FgsError):
+        fgs.Model(fgs.FGS_GMM, 8, 8, p)
+    m.close()
