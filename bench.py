@@ -38,6 +38,31 @@ def pbas_bytes_per_px(N=N_PBAS):
     return 4 * N + 2 * (16 + 16 + 8) + 6
 
 
+def _kv(path):
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(" "):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def measured_traffic(kernel_file: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the kernel source as it is now (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    kv = _kv(path)
+    src = os.path.join(ROOT, kv.get("source", ""))
+    if not os.path.isfile(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("source_sha256_16"):
+        return None
+    return float(kv["hbm_bytes_per_dispatch"])
+
+
 def _gen(args):
     from synth import Scene, preset
     t0, n = args
@@ -63,7 +88,7 @@ def cpu_baseline(rgb, depth):
     from oracle.pbas import PbasParams, PbasRef
     g = GmmRef(H, W, GmmParams(Kc=KC, Kd=KD))
     p = PbasRef(H, W, PbasParams(N=N_PBAS))
-    n_g, n_p = 3, 2
+    n_g, n_p = 12, 8
     # PBAS fill frames (no classification) are set up untimed by copying frames into the buffer
     for k in range(N_PBAS):
         p.step(rgb[k % len(rgb)], depth[k % len(depth)])
@@ -192,12 +217,17 @@ def main():
                    "H": H, "W": W, "gmm_K": KC, "pbas_N": N_PBAS, "frames_cycled": F,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom},
+                     "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("pbas_step_1280x720_n35.txt" if dom == "pbas"
+                                                 else "gmm_step_1280x720_k5.txt"),
+                     "kernel": dom + "_step", "algorithmic_bytes_per_launch": (p_b if dom == "pbas" else g_b) * npx},
         "kernels": {
             "gmm_step": {"avg_ms": round(gmm_ms, 5), "bytes_per_px": g_b, "GBs": round(g_gbs, 1),
+                         "traffic": measured_traffic("gmm_step_1280x720_k5.txt"),
                          "Mpx_per_s": round(npx / (gmm_ms * 1e-3) / 1e6, 1),
                          "frac": round(g_gbs / HBM_PEAK_GBS, 4)},
             "pbas_step": {"avg_ms": round(pbas_ms, 5), "bytes_per_px": p_b, "GBs": round(p_gbs, 1),
+                          "traffic": measured_traffic("pbas_step_1280x720_n35.txt"),
                           "Mpx_per_s": round(npx / (pbas_ms * 1e-3) / 1e6, 1),
                           "frac": round(p_gbs / HBM_PEAK_GBS, 4)},
         },

@@ -212,6 +212,18 @@ fgs_status fgs_stream(const fgs_model* m, void** hip_stream);
 fgs_status fgs_device_bytes(const fgs_model* m, size_t* bytes);
 
 /*
+ * How the model's per-frame state traffic treats the last-level (Infinity)
+ * cache.  The state is read and written once per frame, so it is either kept
+ * cache-resident between frames (worth it while all live models fit) or
+ * streamed with non-temporal accesses.  FGS_CACHE_AUTO (default) streams once
+ * the device bytes of all live models on the device exceed the threshold
+ * FGS_STREAMING_THRESHOLD_MB (environment, default 192).  Results are identical
+ * under every policy.  INVALID_ARG for an unknown policy.
+ */
+typedef enum fgs_cache_policy { FGS_CACHE_AUTO = 0, FGS_CACHE_KEEP = 1, FGS_CACHE_STREAM = 2 } fgs_cache_policy;
+fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy);
+
+/*
  * Diagnostics.
  * fgs_philox4x32_10: for i < n, out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3],
  *   key = (seed low 32 bits, seed high 32 bits)) (Salmon et al., SC'11) -- the

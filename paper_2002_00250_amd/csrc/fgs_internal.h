@@ -27,6 +27,7 @@ struct GmmConsts {
 
 struct GmmStepArgs {
     float4* state;
+    int32_t streaming;  // 1: non-temporal state traffic (working set beyond the last-level cache)
     uint8_t* mask;
     const uint8_t* rgb;
     const uint8_t* depth;  // uint16 rows, addressed in bytes
@@ -76,6 +77,7 @@ struct PbasStepArgs {
     int32_t H, W, npix;
     uint32_t t;            // frame index
     int32_t apply_pending; // intents of frame t-1 still to be applied
+    int32_t streaming;     // 1: non-temporal sample traffic (working set beyond the last-level cache)
     PbasConsts c;
 };
 

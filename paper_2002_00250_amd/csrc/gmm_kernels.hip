@@ -25,6 +25,30 @@ namespace {
 
 constexpr int kBlock = 256;
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// State planes are touched once per frame.  When the device's resident model
+// state exceeds the last-level (Infinity) cache the kernels stream it with
+// non-temporal loads and stores; otherwise ordinary accesses let a cache-sized
+// working set stay resident between frames.
+template <bool NT>
+__device__ __forceinline__ float4 ld_state(const float4* p) {
+    if constexpr (NT) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+        return make_float4(v.x, v.y, v.z, v.w);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void st_state(float4* p, float4 v) {
+    if constexpr (NT) {
+        f32x4 w = {v.x, v.y, v.z, v.w};
+        __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
+    } else {
+        *p = v;
+    }
+}
+
 template <int K, int C>
 struct Mix {
     float w[K];
@@ -145,7 +169,7 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
     }
 }
 
-template <int KC, int KD>
+template <int KC, int KD, bool NT>
 __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     constexpr int E = (KC + 3 * KD + 3) / 4;
     const int p = blockIdx.x * kBlock + threadIdx.x;
@@ -163,10 +187,10 @@ __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     float4 core[KC];
     float ex[4 * E];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) core[k] = st[(int64_t)k * a.npix + p];
+    for (int k = 0; k < KC; ++k) core[k] = ld_state<NT>(st + (int64_t)k * a.npix + p);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const float4 f = st[(int64_t)(KC + e) * a.npix + p];
+        const float4 f = ld_state<NT>(st + (int64_t)(KC + e) * a.npix + p);
         ex[4 * e + 0] = f.x;
         ex[4 * e + 1] = f.y;
         ex[4 * e + 2] = f.z;
@@ -207,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     float4* so = a.state;
 #pragma unroll
     for (int k = 0; k < KC; ++k)
-        so[(int64_t)k * a.npix + p] = make_float4(mc.w[k], mc.mu[k][0], mc.mu[k][1], mc.mu[k][2]);
+        st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.w[k], mc.mu[k][0], mc.mu[k][1], mc.mu[k][2]));
 #pragma unroll
     for (int k = 0; k < KC; ++k) ex[k] = mc.v[k];
 #pragma unroll
@@ -218,8 +242,8 @@ __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     }
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        so[(int64_t)(KC + e) * a.npix + p] =
-            make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]);
+        st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,
+                  make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]));
 }
 
 // Fresh model: w = 0, mu = 0, v = v_init (both mixtures).
@@ -289,7 +313,10 @@ __global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd
 template <int KC, int KD>
 hipError_t launch_step_t(const GmmStepArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)((a.npix + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((gmm_step_kernel<KC, KD>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (a.streaming)
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

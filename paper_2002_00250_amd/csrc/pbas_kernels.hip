@@ -39,6 +39,19 @@ __device__ __forceinline__ uint8_t* byte_at(uint32_t* plane0, int64_t npix, int 
     return reinterpret_cast<uint8_t*>(plane0 + (int64_t)slot * npix + p) + j;
 }
 
+// Sample planes are touched once per frame: non-temporal when the device's
+// resident model state exceeds the last-level cache (see gmm_kernels.hip).
+template <bool NT>
+__device__ __forceinline__ uint32_t ld_sample(const uint32_t* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT>
+__device__ __forceinline__ void st_sample(uint32_t* p, uint32_t v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Stage the intents of the tile and its 1-pixel halo into LDS.
 __device__ __forceinline__ void stage_intents(uint64_t* lds, const uint64_t* __restrict__ intents,
                                               int x0, int y0, int H, int W) {
@@ -81,9 +94,34 @@ __device__ __forceinline__ void apply_pending(const uint64_t* lds, int lx, int l
 // partial-line write.  The Philox draws and the 1/T tests do not depend on the
 // classification, so the candidate self-update slots are known first and their
 // D-history bytes are fetched before the samples, off the critical path.
-template <int NMAX>
+// Gather the neighbour writes aimed at pixel (lx,ly) into per-channel slot
+// bit-planes: plane j, word w holds slots 32w..32w+31.  Each lane touches only its
+// own words of `pend` (layout [word][lane]), so no atomics and no barrier.
+template <int PW>
+__device__ __forceinline__ void gather_pending(const uint64_t* lds, uint32_t* pend, int lx, int ly,
+                                               int tid, uint32_t lastw, int N) {
+    const bool depth_ok = (lastw >> 24) != 0u;  // y had depth at that frame
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int ox = nb_dx(d), oy = nb_dy(d);
+        const uint64_t v = lds[(ly + 1 + oy) * kHaloW + (lx + 1 + ox)];
+        if (v == 0) continue;
+        const uint32_t want = 0x8u | (uint32_t)(7 - d);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t f = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
+            const int slot = (int)(f & 0x3Fu);
+            if ((f >> 12) != want || slot >= N || (j == 3 && !depth_ok)) continue;
+            pend[(j * PW + (slot >> 5)) * kBlock + tid] |= 1u << (slot & 31);
+        }
+    }
+}
+
+template <int NMAX, bool NT>
 __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
+    constexpr int PW = (NMAX + 31) / 32;  // words per channel bit-plane
     __shared__ uint64_t lds[kHaloW * kHaloH];
+    __shared__ uint32_t pend[4 * PW * kBlock];
     const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
     const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
     const int x = x0 + lx, y = y0 + ly;
@@ -91,7 +129,10 @@ __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
     const int64_t npix = a.npix;
     const int N = a.c.N;
 
+    const int tid = threadIdx.x;
     if (a.apply_pending) {
+#pragma unroll
+        for (int w = 0; w < 4 * PW; ++w) pend[w * kBlock + tid] = 0u;
         stage_intents(lds, a.m.intents[(a.t - 1u) & 1u], x0, y0, H, W);
         __syncthreads();
     }
@@ -136,13 +177,32 @@ __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) dold[j] = cand[j] ? (int)*byte_at(a.m.dhist, npix, ks[j], p, j) : 0;
 
-    // Frame t-1's neighbour writes into this pixel, before it is classified.
-    if (a.apply_pending) apply_pending(lds, lx, ly, lastw, a.m.samples, npix, p, N);
-
     uint32_t sm[NMAX];
-    const uint32_t* sp = a.m.samples + p;  // may alias the pending byte stores above
+    const uint32_t* sp = a.m.samples + p;
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) sm[k] = k < N ? sp[(int64_t)k * npix] : 0u;
+    for (int k = 0; k < NMAX; ++k) sm[k] = k < N ? ld_sample<NT>(sp + (int64_t)k * npix) : 0u;
+
+    // Frame t-1's neighbour writes into this pixel, before it is classified: slot k
+    // of channel j takes this pixel's previous value where bit k of plane j is set.
+    if (a.apply_pending) {
+        gather_pending<PW>(lds, pend, lx, ly, tid, lastw, N);
+        uint32_t pw[4][PW];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int w = 0; w < PW; ++w) pw[j][w] = pend[(j * PW + w) * kBlock + tid];
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            const int w = k >> 5, b = k & 31;
+            // all-ones where the bit is set, then one byte lane per channel
+            const uint32_t m0 = (uint32_t)((int32_t)(pw[0][w] << (31 - b)) >> 31);
+            const uint32_t m1 = (uint32_t)((int32_t)(pw[1][w] << (31 - b)) >> 31);
+            const uint32_t m2 = (uint32_t)((int32_t)(pw[2][w] << (31 - b)) >> 31);
+            const uint32_t m3 = (uint32_t)((int32_t)(pw[3][w] << (31 - b)) >> 31);
+            const uint32_t bm = (m0 & 0x000000FFu) | (m1 & 0x0000FF00u) | (m2 & 0x00FF0000u) | (m3 & 0xFF000000u);
+            sm[k] = (sm[k] & ~bm) | (lastw & bm);
+        }
+    }
 
     // Classification: an integer distance d is within R iff d <= ceil(R) - 1.
     int thr[4];
@@ -223,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
     uint32_t* so = a.m.samples + p;
 #pragma unroll
     for (int k = 0; k < NMAX; ++k)
-        if (k < N) so[(int64_t)k * npix] = sm[k];
+        if (k < N) st_sample<NT>(so + (int64_t)k * npix, sm[k]);
     a.m.R[p] = make_float4(R[0], R[1], R[2], R[3]);
     a.m.T[p] = make_float4(T[0], T[1], T[2], T[3]);
     a.m.S[p] = make_uint2((uint32_t)S[0] | ((uint32_t)S[1] << 16), (uint32_t)S[2] | ((uint32_t)S[3] << 16));
@@ -293,6 +353,22 @@ __global__ void pbas_import_rts_kernel(PbasPlanes m, int npix, const float* rt, 
 
 inline unsigned blocks1d(int n) { return (unsigned)((n + 255) / 256); }
 
+template <int NMAX>
+void launch_step_nt(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
+    if (a.streaming) hipLaunchKernelGGL((pbas_step_kernel<NMAX, true>), grid, dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((pbas_step_kernel<NMAX, false>), grid, dim3(kBlock), 0, s, a);
+}
+
+// Register capacity for the N sample words: the smallest instantiated NMAX >= N.
+void launch_step_n(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
+    const int n = a.c.N;
+    if (n <= 8) launch_step_nt<8>(a, grid, s);
+    else if (n <= 16) launch_step_nt<16>(a, grid, s);
+    else if (n <= 24) launch_step_nt<24>(a, grid, s);
+    else if (n <= 40) launch_step_nt<40>(a, grid, s);
+    else launch_step_nt<64>(a, grid, s);
+}
+
 }  // namespace
 
 hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConsts& c,
@@ -308,12 +384,7 @@ hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
         hipLaunchKernelGGL(pbas_fill_kernel, dim3(blocks1d(a.npix)), dim3(256), 0, s, a);
     } else {
         const dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH);
-        const int n = a.c.N;
-        if (n <= 8) hipLaunchKernelGGL(pbas_step_kernel<8>, grid, dim3(kBlock), 0, s, a);
-        else if (n <= 16) hipLaunchKernelGGL(pbas_step_kernel<16>, grid, dim3(kBlock), 0, s, a);
-        else if (n <= 24) hipLaunchKernelGGL(pbas_step_kernel<24>, grid, dim3(kBlock), 0, s, a);
-        else if (n <= 40) hipLaunchKernelGGL(pbas_step_kernel<40>, grid, dim3(kBlock), 0, s, a);
-        else hipLaunchKernelGGL(pbas_step_kernel<64>, grid, dim3(kBlock), 0, s, a);
+        launch_step_n(a, grid, s);
     }
     return hipGetLastError();
 }

@@ -4,8 +4,10 @@
 // per-pixel work is done by the kernels in gmm_kernels.hip / pbas_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -45,6 +47,20 @@ static_assert(sizeof(StateHeader) == kHeaderBytes, "state header is 64 bytes");
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+// Device bytes held by live models, per device: the kernels stream state with
+// non-temporal accesses once this exceeds what the last-level cache can keep.
+constexpr int kMaxDevices = 64;
+std::atomic<int64_t> g_resident[kMaxDevices];
+
+int64_t streaming_threshold() {
+    static const int64_t v = [] {
+        const char* e = std::getenv("FGS_STREAMING_THRESHOLD_MB");
+        const long long mb = e ? std::atoll(e) : 192;  // below the 256 MB Infinity Cache
+        return (int64_t)mb << 20;
+    }();
+    return v;
+}
+
 }  // namespace
 
 struct fgs_model {
@@ -70,6 +86,7 @@ struct fgs_model {
     int64_t t;          // frames pushed
     bool pending;       // PBAS: intents of frame t-1 not yet applied
     bool poisoned;
+    int32_t cache_policy;  // fgs_cache_policy
 };
 
 namespace {
@@ -144,6 +161,13 @@ fgs_status ensure_staging(fgs_model* m) {
     FGS_HIP(m, hipEventCreateWithFlags(&m->stage_done, hipEventDisableTiming));
     m->stage_busy = false;
     return FGS_OK;
+}
+
+bool use_streaming(const fgs_model* m) {
+    if (m->cache_policy == FGS_CACHE_STREAM) return true;
+    if (m->cache_policy == FGS_CACHE_KEEP) return false;
+    const int d = m->device >= 0 && m->device < kMaxDevices ? m->device : 0;
+    return g_resident[d].load(std::memory_order_relaxed) > streaming_threshold();
 }
 
 fgs_status flush_pending(fgs_model* m) {
@@ -324,12 +348,15 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         delete m;
         return fail(FGS_ERR_DEVICE, "model initialisation: %s", hipGetErrorString(e));
     }
+    m->cache_policy = FGS_CACHE_AUTO;
+    if (m->device >= 0 && m->device < kMaxDevices) g_resident[m->device] += (int64_t)m->dev_bytes;
     *out = m;
     return FGS_OK;
 }
 
 fgs_status fgs_destroy(fgs_model* m) {
     if (!m) return FGS_OK;
+    if (m->device >= 0 && m->device < kMaxDevices) g_resident[m->device] -= (int64_t)m->dev_bytes;
     (void)hipStreamSynchronize(m->stream);
     if (m->dev) (void)hipFree(m->dev);
     if (m->dev_in) (void)hipFree(m->dev_in);
@@ -391,6 +418,7 @@ fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
         a.H = m->H;
         a.W = m->W;
         a.npix = m->npix;
+        a.streaming = use_streaming(m) ? 1 : 0;
         a.c = m->gc;
         FGS_HIP(m, gmm_launch_step(a, m->gp.Kc, m->gp.Kd, m->stream));
     } else {
@@ -405,6 +433,7 @@ fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
         a.npix = m->npix;
         a.t = (uint32_t)m->t;
         a.apply_pending = m->pending ? 1 : 0;
+        a.streaming = use_streaming(m) ? 1 : 0;
         a.c = m->pc;
         FGS_HIP(m, pbas_launch_step(a, m->stream));
         m->pending = m->t >= m->pp.N;
@@ -557,6 +586,14 @@ fgs_status fgs_device_bytes(const fgs_model* m, size_t* bytes) {
     size_t b = m->dev_bytes;
     if (m->dev_in) b += align256((size_t)m->npix * 3) + align256((size_t)m->npix * 2);
     *bytes = b;
+    return FGS_OK;
+}
+
+fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy) {
+    if (!m) return fail(FGS_ERR_INVALID_ARG, "model is NULL");
+    if (policy != FGS_CACHE_AUTO && policy != FGS_CACHE_KEEP && policy != FGS_CACHE_STREAM)
+        return fail(FGS_ERR_INVALID_ARG, "unknown cache policy %d", policy);
+    m->cache_policy = policy;
     return FGS_OK;
 }
 

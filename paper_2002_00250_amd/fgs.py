@@ -27,6 +27,9 @@ FGS_GMM = 1
 FGS_PBAS = 2
 FGS_MEM_HOST = 0
 FGS_MEM_DEVICE = 1
+FGS_CACHE_AUTO = 0
+FGS_CACHE_KEEP = 1
+FGS_CACHE_STREAM = 2
 STATE_HEADER_BYTES = 64
 
 
@@ -82,6 +85,7 @@ def _load():
         "fgs_sync": (S, [c_void_p]),
         "fgs_stream": (S, [c_void_p, POINTER(c_void_p)]),
         "fgs_device_bytes": (S, [c_void_p, POINTER(c_size_t)]),
+        "fgs_set_cache_policy": (S, [c_void_p, c_int32]),
         "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
         "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
     }
@@ -188,6 +192,10 @@ def fgs_device_bytes(m: int) -> int:
     out = c_size_t()
     _check(_load().fgs_device_bytes(c_void_p(m), byref(out)))
     return out.value
+
+
+def fgs_set_cache_policy(m: int, policy: int) -> None:
+    _check(_load().fgs_set_cache_policy(c_void_p(m), policy))
 
 
 def fgs_philox4x32_10(seed: int, ctr: int, out: int, n: int, hip_stream: int | None = None) -> None:
