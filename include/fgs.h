@@ -224,6 +224,42 @@ typedef enum fgs_cache_policy { FGS_CACHE_AUTO = 0, FGS_CACHE_KEEP = 1, FGS_CACH
 fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy);
 
 /*
+ * GMM adjoint over a window of frames (gradient of a loss on the pre-update scores
+ * with respect to theta = (alpha, lambda, w_depth)).
+ *
+ * The window starts from a fresh GMM (Sec. 3.1; constants other than theta from
+ * `params`, which must have Kc == Kd in 1..5) and runs T frames.  Frame t yields
+ * the score Z_t = (delta_c - lambda^2) + w_depth*(delta_d - lambda^2) of the
+ * pre-update model (terms only where the model has data, depth only where
+ * D > 0; Z_t = 0 and has_term = 0 where neither exists) -- the quantity the mask
+ * thresholds at zero.  fgs_gmm_window_forward records the discrete choices of
+ * every step (background Gaussian attaining delta, matched Gaussian or
+ * replacement, variance floor, ranking) and checkpoints the means and variances
+ * every `checkpoint_every` frames.  fgs_gmm_window_backward holds those choices
+ * fixed and returns dtheta[i] = sum over t, pixels of dZ[t] * dZ_t/dtheta_i,
+ * replaying each segment from its checkpoint; the sum is reduced in a fixed
+ * order (deterministic).
+ *
+ * All arrays are device memory, dense, in the window's stream order:
+ * theta float[3]; rgb uint8[T][H][W][3]; depth uint16[T][H][W]; Z float[T][H][W];
+ * has_term uint8[T][H][W]; dZ float[T][H][W]; dtheta double[3].  The caller
+ * keeps the frames unchanged between forward and backward.  `hip_stream` as in
+ * fgs_create.  Errors: INVALID_ARG, UNSUPPORTED (K), OUT_OF_MEMORY, BAD_STATE
+ * (backward or records before forward), DEVICE.
+ */
+typedef struct fgs_gmm_window fgs_gmm_window;
+fgs_status fgs_gmm_window_create(int32_t T, int32_t H, int32_t W, const fgs_gmm_params* params,
+                                 int32_t checkpoint_every, void* hip_stream, fgs_gmm_window** out);
+fgs_status fgs_gmm_window_forward(fgs_gmm_window* w, const float* theta, const uint8_t* rgb,
+                                  const uint16_t* depth, float* Z, uint8_t* has_term);
+fgs_status fgs_gmm_window_backward(fgs_gmm_window* w, const float* theta, const uint8_t* rgb,
+                                   const uint16_t* depth, const float* dZ, double* dtheta);
+/* Copy the last forward's records (uint64[T][H][W], layout documented in the
+ * library source) to host or device memory. */
+fgs_status fgs_gmm_window_records(fgs_gmm_window* w, uint64_t* out, fgs_mem where);
+fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w);
+
+/*
  * Diagnostics.
  * fgs_philox4x32_10: for i < n, out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3],
  *   key = (seed low 32 bits, seed high 32 bits)) (Salmon et al., SC'11) -- the

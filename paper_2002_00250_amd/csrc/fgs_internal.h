@@ -45,6 +45,30 @@ hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, in
 hipError_t gmm_launch_import(float4* state, const float* in, int Kc, int Kd, int npix,
                              hipStream_t s);
 
+// --------------------------------------------------------- GMM adjoint ----
+// A window of T frames from a fresh model; checkpoints every E frames.  Frames
+// are dense device arrays rgb[T][npix][3], depth[T][npix].  Snapshot planes hold
+// means and variances only (6K floats per pixel).
+struct GmmWindowArgs {
+    int32_t T, H, W, npix, E, nseg;
+    GmmConsts c;            // alpha, lam, w_depth unused: theta comes from device memory
+    const float* theta;     // device [3]: alpha, lambda, w_depth
+    const uint8_t* rgb;
+    const uint16_t* depth;
+    float* Z;               // [T][npix] pre-update scores (0 where no term)
+    uint8_t* has;           // [T][npix] 1 where Z has a term
+    uint64_t* rec;          // [T][npix] recorded discrete choices
+    float* ckpt;            // [nseg][6K][npix]
+    float* scratch;         // [E][6K][npix]
+    const float* dZ;        // [T][npix]
+    double* partial;        // [blocks][3]
+    double* dtheta;         // [3]
+};
+bool gmm_window_supported(int K);
+int gmm_window_blocks(int npix);
+hipError_t gmm_window_launch_forward(const GmmWindowArgs& a, int K, hipStream_t s);
+hipError_t gmm_window_launch_backward(const GmmWindowArgs& a, int K, hipStream_t s);
+
 // --------------------------------------------------------------- PBAS ----
 // Device layout: samples[N] and dhist[N] uint32 planes (bytes R,G,B,depth), R and
 // T as one float4 per pixel, S as four uint16 per pixel (uint2), `last` = the

@@ -1,0 +1,174 @@
+// The per-pixel step of one Gaussian mixture (colour: C = 3 channels, depth:
+// C = 1), shared by the plain per-frame kernel and the adjoint window kernels so
+// that both run the same IEEE binary32 operations in the same order (Sec. 3.1 and
+// the Stauffer-Grimson recursion it builds on).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fgs {
+
+template <int K, int C>
+struct Mix {
+    float w[K];
+    float mu[K][C];
+    float v[K];
+};
+
+// The discrete choices of one step, recorded for the adjoint: the Gaussian that
+// attains delta, the matched Gaussian (-1: replacement), whether the variance floor
+// applied, and the ranking (3 bits per rank: the pre-ranking index now at that rank).
+struct MixRec {
+    int argmin;
+    int kstar;
+    bool clamp;
+    uint32_t perm;
+};
+
+// Classify on the pre-update mixture (used, delta) and, if `active`, update it in
+// place.  With REC, also fill *rec.
+template <int K, int C, bool REC>
+__device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
+                                             float alpha, float lam2, float T_bg, float w_init,
+                                             float v_init, float v_min, bool& used,
+                                             float& delta, MixRec* rec) {
+    float q[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float e = X[0] - m.mu[k][0];
+        float d2 = e * e;
+#pragma unroll
+        for (int c = 1; c < C; ++c) {
+            e = X[c] - m.mu[k][c];
+            d2 = d2 + e * e;
+        }
+        q[k] = d2 / m.v[k];
+    }
+
+    used = m.w[0] > 0.0f;
+    int nused = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) nused += (m.w[k] > 0.0f) ? 1 : 0;
+    int B = nused;
+    bool found = false;
+    float cum = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cum = cum + m.w[k];
+        if (!found && cum > T_bg) {
+            B = k + 1;
+            found = true;
+        }
+    }
+    // delta = min over the background Gaussians; the first index attaining it
+    delta = q[0];
+    int amin = 0;
+#pragma unroll
+    for (int k = 1; k < K; ++k)
+        if (k < B && q[k] < delta) {
+            delta = q[k];
+            amin = k;
+        }
+    if (REC) {
+        rec->argmin = amin;
+        rec->kstar = -1;
+        rec->clamp = false;
+        uint32_t id = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) id |= (uint32_t)k << (3 * k);
+        rec->perm = id;
+    }
+
+    if (!active) return;
+
+    int ks = -1;
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k)
+        if (m.w[k] > 0.0f && q[k] < lam2) ks = k;
+
+    const float a = 1.0f - alpha;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float wk = a * m.w[k];
+        if (k == ks) wk = wk + alpha;
+        m.w[k] = wk;
+    }
+    if (ks >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (k != ks) continue;
+            float mn[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) mn[c] = m.mu[k][c] + alpha * (X[c] - m.mu[k][c]);
+            float e = X[0] - mn[0];
+            float d2 = e * e;
+#pragma unroll
+            for (int c = 1; c < C; ++c) {
+                e = X[c] - mn[c];
+                d2 = d2 + e * e;
+            }
+            float vn = m.v[k] + alpha * (d2 - m.v[k]);
+            if (REC) rec->clamp = vn < v_min;
+            vn = fmaxf(vn, v_min);
+#pragma unroll
+            for (int c = 0; c < C; ++c) m.mu[k][c] = mn[c];
+            m.v[k] = vn;
+        }
+    } else {
+        m.w[K - 1] = w_init;
+#pragma unroll
+        for (int c = 0; c < C; ++c) m.mu[K - 1][c] = X[c];
+        m.v[K - 1] = v_init;
+    }
+
+    float S = m.w[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) S = S + m.w[k];
+#pragma unroll
+    for (int k = 0; k < K; ++k) m.w[k] = m.w[k] / S;
+
+    // Rank: insertion network of adjacent compare-exchanges, strictly-greater
+    // swaps only, so equal keys keep their order (stable).
+    if (REC) rec->kstar = ks;
+    float key[K];
+    int idx[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        key[k] = m.w[k] / sqrtf(m.v[k]);
+        idx[k] = k;
+    }
+#pragma unroll
+    for (int i = 1; i < K; ++i) {
+#pragma unroll
+        for (int j = i; j > 0; --j) {
+            const bool sw = key[j] > key[j - 1];
+            float t;
+#define FGS_CSWAP(A, B)      \
+    t = sw ? (A) : (B);      \
+    (A) = sw ? (B) : (A);    \
+    (B) = t;
+            FGS_CSWAP(key[j], key[j - 1]);
+            {
+                const int ti = sw ? idx[j] : idx[j - 1];
+                idx[j] = sw ? idx[j - 1] : idx[j];
+                idx[j - 1] = ti;
+            }
+            FGS_CSWAP(m.w[j], m.w[j - 1]);
+            FGS_CSWAP(m.v[j], m.v[j - 1]);
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                FGS_CSWAP(m.mu[j][c], m.mu[j - 1][c]);
+            }
+#undef FGS_CSWAP
+        }
+    }
+    if (REC) {
+        uint32_t pr = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) pr |= (uint32_t)idx[k] << (3 * k);
+        rec->perm = pr;
+    }
+}
+
+}  // namespace fgs

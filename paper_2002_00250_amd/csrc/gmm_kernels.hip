@@ -18,6 +18,7 @@
 //     Gaussian K-1 = (w_init, X, v_init); w /= sum(w); stable sort by w/sqrt(v).
 #include "device_common.h"
 #include "fgs_internal.h"
+#include "gmm_device.h"
 
 namespace fgs {
 
@@ -46,126 +47,6 @@ __device__ __forceinline__ void st_state(float4* p, float4 v) {
         __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
     } else {
         *p = v;
-    }
-}
-
-template <int K, int C>
-struct Mix {
-    float w[K];
-    float mu[K][C];
-    float v[K];
-};
-
-// Classify on the pre-update mixture (used, delta) and, if `active`, update it in place.
-template <int K, int C>
-__device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
-                                             float alpha, float lam2, float T_bg, float w_init,
-                                             float v_init, float v_min, bool& used,
-                                             float& delta) {
-    float q[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        float e = X[0] - m.mu[k][0];
-        float d2 = e * e;
-#pragma unroll
-        for (int c = 1; c < C; ++c) {
-            e = X[c] - m.mu[k][c];
-            d2 = d2 + e * e;
-        }
-        q[k] = d2 / m.v[k];
-    }
-
-    used = m.w[0] > 0.0f;
-    int nused = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) nused += (m.w[k] > 0.0f) ? 1 : 0;
-    int B = nused;
-    bool found = false;
-    float cum = 0.0f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        cum = cum + m.w[k];
-        if (!found && cum > T_bg) {
-            B = k + 1;
-            found = true;
-        }
-    }
-    delta = q[0];
-#pragma unroll
-    for (int k = 1; k < K; ++k)
-        if (k < B) delta = fminf(delta, q[k]);
-
-    if (!active) return;
-
-    int ks = -1;
-#pragma unroll
-    for (int k = K - 1; k >= 0; --k)
-        if (m.w[k] > 0.0f && q[k] < lam2) ks = k;
-
-    const float a = 1.0f - alpha;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        float wk = a * m.w[k];
-        if (k == ks) wk = wk + alpha;
-        m.w[k] = wk;
-    }
-    if (ks >= 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (k != ks) continue;
-            float mn[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) mn[c] = m.mu[k][c] + alpha * (X[c] - m.mu[k][c]);
-            float e = X[0] - mn[0];
-            float d2 = e * e;
-#pragma unroll
-            for (int c = 1; c < C; ++c) {
-                e = X[c] - mn[c];
-                d2 = d2 + e * e;
-            }
-            float vn = m.v[k] + alpha * (d2 - m.v[k]);
-            vn = fmaxf(vn, v_min);
-#pragma unroll
-            for (int c = 0; c < C; ++c) m.mu[k][c] = mn[c];
-            m.v[k] = vn;
-        }
-    } else {
-        m.w[K - 1] = w_init;
-#pragma unroll
-        for (int c = 0; c < C; ++c) m.mu[K - 1][c] = X[c];
-        m.v[K - 1] = v_init;
-    }
-
-    float S = m.w[0];
-#pragma unroll
-    for (int k = 1; k < K; ++k) S = S + m.w[k];
-#pragma unroll
-    for (int k = 0; k < K; ++k) m.w[k] = m.w[k] / S;
-
-    // Rank: insertion network of adjacent compare-exchanges, strictly-greater
-    // swaps only, so equal keys keep their order (stable).
-    float key[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) key[k] = m.w[k] / sqrtf(m.v[k]);
-#pragma unroll
-    for (int i = 1; i < K; ++i) {
-#pragma unroll
-        for (int j = i; j > 0; --j) {
-            const bool sw = key[j] > key[j - 1];
-            float t;
-#define FGS_CSWAP(A, B)      \
-    t = sw ? (A) : (B);      \
-    (A) = sw ? (B) : (A);    \
-    (B) = t;
-            FGS_CSWAP(key[j], key[j - 1]);
-            FGS_CSWAP(m.w[j], m.w[j - 1]);
-            FGS_CSWAP(m.v[j], m.v[j - 1]);
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                FGS_CSWAP(m.mu[j][c], m.mu[j - 1][c]);
-            }
-#undef FGS_CSWAP
-        }
     }
 }
 
@@ -216,10 +97,10 @@ __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     const float lam2 = a.c.lam * a.c.lam;
     bool used_c, used_d;
     float dc, dd;
-    mixture_step<KC, 3>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
-                        a.c.v_min_c, used_c, dc);
-    mixture_step<KD, 1>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
-                        a.c.v_min_d, used_d, dd);
+    mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
+                        a.c.v_min_c, used_c, dc, nullptr);
+    mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
+                        a.c.v_min_d, used_d, dd, nullptr);
 
     const bool term_c = used_c;
     const bool term_d = valid && used_d;

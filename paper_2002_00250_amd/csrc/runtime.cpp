@@ -597,6 +597,145 @@ fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy) {
     return FGS_OK;
 }
 
+// ------------------------------------------------------------ GMM adjoint
+}  // extern "C"
+
+struct fgs_gmm_window {
+    int32_t T, H, W, npix, K, E, nseg;
+    GmmConsts c;
+    hipStream_t stream;
+    bool own_stream;
+    uint8_t* dev;
+    uint64_t* rec;
+    float* ckpt;
+    float* scratch;
+    double* partial;
+    bool have_forward;
+};
+
+extern "C" {
+
+fgs_status fgs_gmm_window_create(int32_t T, int32_t H, int32_t W, const fgs_gmm_params* params,
+                                 int32_t checkpoint_every, void* hip_stream, fgs_gmm_window** out) {
+    if (!out) return fail(FGS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    fgs_gmm_params p;
+    fgs_gmm_params_default(&p);
+    if (params) std::memcpy(&p, params, sizeof p);
+    fgs_status st = check_gmm(p);
+    if (st != FGS_OK) return st;
+    if (p.Kc != p.Kd || !gmm_window_supported(p.Kc))
+        return fail(FGS_ERR_UNSUPPORTED, "the adjoint supports Kc = Kd in 1..5, not (%d, %d)", p.Kc, p.Kd);
+    if (T < 1 || H < 1 || W < 1 || (int64_t)H * W > kMaxPixels || checkpoint_every < 1)
+        return fail(FGS_ERR_INVALID_ARG, "bad window T=%d H=%d W=%d E=%d", T, H, W, checkpoint_every);
+    fgs_gmm_window* w = new (std::nothrow) fgs_gmm_window();
+    if (!w) return fail(FGS_ERR_OUT_OF_MEMORY, "host allocation");
+    w->T = T;
+    w->H = H;
+    w->W = W;
+    w->npix = H * W;
+    w->K = p.Kc;
+    w->E = checkpoint_every < T ? checkpoint_every : T;
+    w->nseg = (T + w->E - 1) / w->E;
+    w->c = GmmConsts{p.alpha, p.lambda, p.T_bg, p.w_init, p.v_init_c, p.v_min_c, p.v_init_d,
+                     p.v_min_d, p.w_depth, (uint32_t)p.depth_max_mm};
+    const size_t n = (size_t)w->npix, F = 6 * (size_t)w->K;
+    const size_t o_rec = 0;
+    const size_t o_ckpt = o_rec + align256((size_t)T * n * 8);
+    const size_t o_scr = o_ckpt + align256((size_t)w->nseg * F * n * 4);
+    const size_t o_par = o_scr + align256((size_t)w->E * F * n * 4);
+    const size_t total = o_par + align256((size_t)gmm_window_blocks(w->npix) * 3 * 8);
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        w->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&w->stream, hipStreamNonBlocking);
+        w->own_stream = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&w->dev, total);
+    if (e != hipSuccess) {
+        if (w->own_stream) (void)hipStreamDestroy(w->stream);
+        delete w;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "window allocation of %zu bytes: %s", total, hipGetErrorString(e));
+    }
+    w->rec = reinterpret_cast<uint64_t*>(w->dev + o_rec);
+    w->ckpt = reinterpret_cast<float*>(w->dev + o_ckpt);
+    w->scratch = reinterpret_cast<float*>(w->dev + o_scr);
+    w->partial = reinterpret_cast<double*>(w->dev + o_par);
+    *out = w;
+    return FGS_OK;
+}
+
+static GmmWindowArgs window_args(fgs_gmm_window* w, const float* theta, const uint8_t* rgb,
+                                 const uint16_t* depth) {
+    GmmWindowArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.T = w->T;
+    a.H = w->H;
+    a.W = w->W;
+    a.npix = w->npix;
+    a.E = w->E;
+    a.nseg = w->nseg;
+    a.c = w->c;
+    a.theta = theta;
+    a.rgb = rgb;
+    a.depth = depth;
+    a.rec = w->rec;
+    a.ckpt = w->ckpt;
+    a.scratch = w->scratch;
+    a.partial = w->partial;
+    return a;
+}
+
+fgs_status fgs_gmm_window_forward(fgs_gmm_window* w, const float* theta, const uint8_t* rgb,
+                                  const uint16_t* depth, float* Z, uint8_t* has_term) {
+    if (!w || !theta || !rgb || !depth || !Z || !has_term) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (((uintptr_t)depth & 1) || ((uintptr_t)Z & 3) || ((uintptr_t)theta & 3))
+        return fail(FGS_ERR_INVALID_ARG, "misaligned device buffer");
+    GmmWindowArgs a = window_args(w, theta, rgb, depth);
+    a.Z = Z;
+    a.has = has_term;
+    hipError_t e = gmm_window_launch_forward(a, w->K, w->stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "window forward: %s", hipGetErrorString(e));
+    w->have_forward = true;
+    return FGS_OK;
+}
+
+fgs_status fgs_gmm_window_backward(fgs_gmm_window* w, const float* theta, const uint8_t* rgb,
+                                   const uint16_t* depth, const float* dZ, double* dtheta) {
+    if (!w || !theta || !rgb || !depth || !dZ || !dtheta) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (!w->have_forward) return fail(FGS_ERR_BAD_STATE, "backward before forward");
+    if (((uintptr_t)depth & 1) || ((uintptr_t)dZ & 3) || ((uintptr_t)dtheta & 7) || ((uintptr_t)theta & 3))
+        return fail(FGS_ERR_INVALID_ARG, "misaligned device buffer");
+    GmmWindowArgs a = window_args(w, theta, rgb, depth);
+    a.dZ = dZ;
+    a.dtheta = dtheta;
+    hipError_t e = gmm_window_launch_backward(a, w->K, w->stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "window backward: %s", hipGetErrorString(e));
+    return FGS_OK;
+}
+
+fgs_status fgs_gmm_window_records(fgs_gmm_window* w, uint64_t* out, fgs_mem where) {
+    if (!w || !out) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (!w->have_forward) return fail(FGS_ERR_BAD_STATE, "no forward has run");
+    const size_t bytes = (size_t)w->T * w->npix * 8;
+    hipError_t e = hipMemcpyAsync(out, w->rec, bytes,
+                                  where == FGS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                  w->stream);
+    if (e == hipSuccess && where == FGS_MEM_HOST) e = hipStreamSynchronize(w->stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "records copy: %s", hipGetErrorString(e));
+    return FGS_OK;
+}
+
+fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w) {
+    if (!w) return FGS_OK;
+    (void)hipStreamSynchronize(w->stream);
+    (void)hipFree(w->dev);
+    if (w->own_stream) (void)hipStreamDestroy(w->stream);
+    delete w;
+    return FGS_OK;
+}
+
 fgs_status fgs_philox4x32_10(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                              void* hip_stream) {
     if (n < 0 || (n > 0 && (!ctr || !out))) return fail(FGS_ERR_INVALID_ARG, "bad philox arguments");

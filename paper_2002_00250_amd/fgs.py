@@ -86,6 +86,12 @@ def _load():
         "fgs_stream": (S, [c_void_p, POINTER(c_void_p)]),
         "fgs_device_bytes": (S, [c_void_p, POINTER(c_size_t)]),
         "fgs_set_cache_policy": (S, [c_void_p, c_int32]),
+        "fgs_gmm_window_create": (S, [c_int32, c_int32, c_int32, POINTER(fgs_gmm_params), c_int32, c_void_p,
+                                      POINTER(c_void_p)]),
+        "fgs_gmm_window_forward": (S, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "fgs_gmm_window_backward": (S, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "fgs_gmm_window_records": (S, [c_void_p, c_void_p, c_int32]),
+        "fgs_gmm_window_destroy": (S, [c_void_p]),
         "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
         "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
     }
@@ -196,6 +202,32 @@ def fgs_device_bytes(m: int) -> int:
 
 def fgs_set_cache_policy(m: int, policy: int) -> None:
     _check(_load().fgs_set_cache_policy(c_void_p(m), policy))
+
+
+def fgs_gmm_window_create(T: int, H: int, W: int, params=None, checkpoint_every: int = 16,
+                          hip_stream: int | None = None) -> int:
+    out = c_void_p()
+    pp = byref(params) if params is not None else None
+    _check(_load().fgs_gmm_window_create(T, H, W, pp, checkpoint_every, c_void_p(hip_stream or 0), byref(out)))
+    return out.value
+
+
+def fgs_gmm_window_forward(w: int, theta: int, rgb: int, depth: int, Z: int, has_term: int) -> None:
+    _check(_load().fgs_gmm_window_forward(c_void_p(w), c_void_p(theta), c_void_p(rgb), c_void_p(depth),
+                                          c_void_p(Z), c_void_p(has_term)))
+
+
+def fgs_gmm_window_backward(w: int, theta: int, rgb: int, depth: int, dZ: int, dtheta: int) -> None:
+    _check(_load().fgs_gmm_window_backward(c_void_p(w), c_void_p(theta), c_void_p(rgb), c_void_p(depth),
+                                           c_void_p(dZ), c_void_p(dtheta)))
+
+
+def fgs_gmm_window_records(w: int, out: int, where: int) -> None:
+    _check(_load().fgs_gmm_window_records(c_void_p(w), c_void_p(out), where))
+
+
+def fgs_gmm_window_destroy(w: int) -> None:
+    _check(_load().fgs_gmm_window_destroy(c_void_p(w)))
 
 
 def fgs_philox4x32_10(seed: int, ctr: int, out: int, n: int, hip_stream: int | None = None) -> None:
