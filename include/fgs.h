@@ -260,6 +260,67 @@ fgs_status fgs_gmm_window_records(fgs_gmm_window* w, uint64_t* out, fgs_mem wher
 fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w);
 
 /*
+ * Multi-stream serving.  Many camera streams on one GPU, every model resident in
+ * device memory, frames batched continuously: a scheduler thread takes the next
+ * queued frame of every stream whose previous frame has finished (at most one
+ * frame per stream in flight, so each stream's frames run in order), copies the
+ * inputs over, runs ONE kernel launch over all of them (mixed resolutions, GMM
+ * and PBAS) and copies the masks back, without waiting for earlier batches; a
+ * completion thread stamps each frame's latency.  Per-stream results are exactly
+ * those of a model driven alone with fgs_push_frame.
+ *
+ * fgs_server_create: `hbm_budget_bytes` caps the device memory of all open
+ *   streams (models, input slots) plus the server's own buffers; up to
+ *   `max_streams` streams; GMM streams must use Kc = Kd = gmm_K (3 or 5), PBAS
+ *   streams N <= pbas_N_max (<= 40).  Uses the current device.
+ * fgs_server_open: admit a stream (params as in fgs_create).  BUSY when the
+ *   budget or the stream slots would be exceeded (nothing is allocated then);
+ *   UNSUPPORTED for a K or N outside the server's classes.
+ * fgs_server_submit: copy one host frame (dense rgb uint8[H][W][3], depth
+ *   uint16[H][W]) into the stream's ring (4 frames) and return a ticket; the
+ *   buffers may be reused at once.  t_arrival_s is the frame's arrival on the
+ *   fgs_server_now() clock (<= 0: now).  BUSY when 4 frames of the stream are
+ *   pending or uncollected.
+ * fgs_server_wait: block until the ticket's frame is done (timeout_ms < 0:
+ *   forever; else BUSY on timeout), copy its mask (host uint8[H][W]; NULL to
+ *   skip), report its latency (completion - arrival, seconds) and release the
+ *   slot.  BAD_STATE if the frame was dropped by fgs_server_close, DEVICE after
+ *   a device error.
+ * fgs_server_close: stop a stream; its frame in flight finishes, queued frames
+ *   are dropped, its device memory returns to the budget.
+ * fgs_server_get_stats: since creation or the last fgs_server_reset_stats:
+ *   completed frames, batches, mean frames per batch, p50 / p99 / max latency,
+ *   completed pixel-frames per second, budget use.  Set struct_size first.
+ * fgs_server_destroy: finish the batches in flight and free everything; no other
+ *   call on the server may run concurrently with it.
+ * All other server calls are thread-safe.
+ */
+typedef struct fgs_server fgs_server;
+typedef struct fgs_server_stats {
+    uint32_t struct_size; /* = sizeof(fgs_server_stats) */
+    int32_t streams_open;
+    int64_t frames_done;
+    int64_t batches;
+    double mean_batch_frames;
+    double p50_latency_s, p99_latency_s, max_latency_s;
+    double mpix_frames_per_s;
+    uint64_t device_bytes_used, device_budget;
+} fgs_server_stats;
+double fgs_server_now(void);
+fgs_status fgs_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32_t gmm_K,
+                             int32_t pbas_N_max, fgs_server** out);
+fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, const void* params,
+                           int32_t* stream_id);
+fgs_status fgs_server_submit(fgs_server* s, int32_t stream_id, const uint8_t* rgb,
+                             const uint16_t* depth, double t_arrival_s, uint64_t* ticket);
+fgs_status fgs_server_wait(fgs_server* s, uint64_t ticket, uint8_t* mask, double* latency_s,
+                           int32_t timeout_ms);
+fgs_status fgs_server_close(fgs_server* s, int32_t stream_id);
+fgs_status fgs_server_get_stats(fgs_server* s, fgs_server_stats* out);
+fgs_status fgs_server_reset_stats(fgs_server* s);
+fgs_status fgs_server_destroy(fgs_server* s);
+
+/*
  * Diagnostics.
  * fgs_philox4x32_10: for i < n, out[4i..4i+3] = Philox4x32-10(ctr[4i..4i+3],
  *   key = (seed low 32 bits, seed high 32 bits)) (Salmon et al., SC'11) -- the

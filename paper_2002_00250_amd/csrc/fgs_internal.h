@@ -114,6 +114,25 @@ hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out
 hipError_t pbas_launch_import(const PbasPlanes& m, int npix, int N, const uint8_t* in,
                               hipStream_t s);
 
+// ------------------------------------------------------------ serving ----
+// One entry of a serving batch: the next frame of one stream.  GMM entries are
+// cut into 256-pixel tiles, PBAS entries into 64x4 tiles (1-D 256-pixel tiles
+// while the model is still filling its samples).
+struct ServeEntry {
+    int32_t algo;     // FGS_GMM or FGS_PBAS
+    int32_t fill;     // PBAS frame < N
+    int32_t tiles_x;  // PBAS tiles per row
+    int32_t ntiles;
+    GmmStepArgs g;
+    PbasStepArgs p;
+};
+bool serve_supported(int gmm_K, int pbas_nmax);
+int serve_pbas_nmax(int N);  // register capacity class of a PBAS model
+// One launch over every tile of every entry (prefix[i] = first tile of entry i,
+// prefix[n] = total), grid-stride over a grid sized to the device.
+hipError_t serve_launch(const ServeEntry* entries, const int32_t* prefix, int n, int total_tiles,
+                        int gmm_K, int pbas_nmax, bool streaming, hipStream_t s);
+
 // -------------------------------------------------------- diagnostics ----
 hipError_t diag_launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                               hipStream_t s);

@@ -26,105 +26,10 @@ namespace {
 
 constexpr int kBlock = 256;
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-// State planes are touched once per frame.  When the device's resident model
-// state exceeds the last-level (Infinity) cache the kernels stream it with
-// non-temporal loads and stores; otherwise ordinary accesses let a cache-sized
-// working set stay resident between frames.
-template <bool NT>
-__device__ __forceinline__ float4 ld_state(const float4* p) {
-    if constexpr (NT) {
-        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
-        return make_float4(v.x, v.y, v.z, v.w);
-    } else {
-        return *p;
-    }
-}
-template <bool NT>
-__device__ __forceinline__ void st_state(float4* p, float4 v) {
-    if constexpr (NT) {
-        f32x4 w = {v.x, v.y, v.z, v.w};
-        __builtin_nontemporal_store(w, reinterpret_cast<f32x4*>(p));
-    } else {
-        *p = v;
-    }
-}
-
 template <int KC, int KD, bool NT>
 __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
-    constexpr int E = (KC + 3 * KD + 3) / 4;
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= a.npix) return;
-    const int y = p / a.W;
-    const int x = p - y * a.W;
-
-    const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
-    const uint32_t dmm = *reinterpret_cast<const uint16_t*>(a.depth + (int64_t)y * a.depth_stride + 2 * x);
-    const float Xc[3] = {(float)px[0], (float)px[1], (float)px[2]};
-    const bool valid = dmm > 0u;
-    const float Xd[1] = {(float)depth_code(dmm, a.c.depth_max_mm)};
-
-    const float4* st = a.state;
-    float4 core[KC];
-    float ex[4 * E];
-#pragma unroll
-    for (int k = 0; k < KC; ++k) core[k] = ld_state<NT>(st + (int64_t)k * a.npix + p);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const float4 f = ld_state<NT>(st + (int64_t)(KC + e) * a.npix + p);
-        ex[4 * e + 0] = f.x;
-        ex[4 * e + 1] = f.y;
-        ex[4 * e + 2] = f.z;
-        ex[4 * e + 3] = f.w;
-    }
-    Mix<KC, 3> mc;
-    Mix<KD, 1> md;
-#pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        mc.w[k] = core[k].x;
-        mc.mu[k][0] = core[k].y;
-        mc.mu[k][1] = core[k].z;
-        mc.mu[k][2] = core[k].w;
-        mc.v[k] = ex[k];
-    }
-#pragma unroll
-    for (int k = 0; k < KD; ++k) {
-        md.w[k] = ex[KC + k];
-        md.mu[k][0] = ex[KC + KD + k];
-        md.v[k] = ex[KC + 2 * KD + k];
-    }
-
-    const float lam2 = a.c.lam * a.c.lam;
-    bool used_c, used_d;
-    float dc, dd;
-    mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
-                        a.c.v_min_c, used_c, dc, nullptr);
-    mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
-                        a.c.v_min_d, used_d, dd, nullptr);
-
-    const bool term_c = used_c;
-    const bool term_d = valid && used_d;
-    const float tc = dc - lam2;
-    const float td = a.c.w_depth * (dd - lam2);
-    const float Z = term_c ? (term_d ? tc + td : tc) : td;
-    a.mask[p] = ((term_c || term_d) && Z >= 0.0f) ? (uint8_t)255 : (uint8_t)0;
-
-    float4* so = a.state;
-#pragma unroll
-    for (int k = 0; k < KC; ++k)
-        st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.w[k], mc.mu[k][0], mc.mu[k][1], mc.mu[k][2]));
-#pragma unroll
-    for (int k = 0; k < KC; ++k) ex[k] = mc.v[k];
-#pragma unroll
-    for (int k = 0; k < KD; ++k) {
-        ex[KC + k] = md.w[k];
-        ex[KC + KD + k] = md.mu[k][0];
-        ex[KC + 2 * KD + k] = md.v[k];
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-        st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,
-                  make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]));
+    if (p < a.npix) gmm_pixel<KC, KD, NT>(a, p);
 }
 
 // Fresh model: w = 0, mu = 0, v = v_init (both mixtures).

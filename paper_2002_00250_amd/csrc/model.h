@@ -1,0 +1,49 @@
+// Internal: the model object behind fgs_model* and the host-side preparation of
+// one frame's launch arguments, shared by fgs_push_frame and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fgs.h"
+#include "fgs_internal.h"
+
+struct fgs_model {
+    fgs_algo algo;
+    int32_t H, W, npix;
+    fgs_gmm_params gp;
+    fgs_pbas_params pp;
+    fgs::GmmConsts gc;
+    fgs::PbasConsts pc;
+    int device;
+    hipStream_t stream;
+    bool own_stream;
+    uint8_t* dev;      // one allocation: state + scratch planes + mask
+    size_t dev_bytes;
+    float4* gmm_state;
+    fgs::PbasPlanes pb;
+    uint8_t* mask;
+    // host-frame staging (allocated on the first host push)
+    uint8_t* host_stage;
+    uint8_t* dev_in;
+    hipEvent_t stage_done;
+    bool stage_busy;
+    int64_t t;          // frames pushed
+    bool pending;       // PBAS: intents of frame t-1 not yet applied
+    bool poisoned;
+    int32_t cache_policy;  // fgs_cache_policy
+};
+
+namespace fgs {
+
+// Thread-local error text + status (fgs_last_error).
+fgs_status set_error(fgs_status s, const char* fmt, ...);
+// Non-temporal state traffic for this model's next launch (cache policy).
+bool model_use_streaming(const fgs_model* m);
+// Launch arguments of the model's next frame read from device frames; advances the
+// model's frame counter and pending-intent flag exactly as a push does.
+void model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
+                    int64_t depth_stride, GmmStepArgs* a);
+void model_next_pbas(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
+                     int64_t depth_stride, PbasStepArgs* a);
+
+}  // namespace fgs

@@ -14,6 +14,7 @@
 
 #include "fgs.h"
 #include "fgs_internal.h"
+#include "model.h"
 
 using namespace fgs;
 
@@ -21,7 +22,9 @@ namespace {
 
 thread_local std::string g_last_error;
 
-fgs_status fail(fgs_status s, const char* fmt, ...) {
+}  // namespace
+
+fgs_status fgs::set_error(fgs_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -29,6 +32,13 @@ fgs_status fail(fgs_status s, const char* fmt, ...) {
     va_end(ap);
     g_last_error = buf;
     return s;
+}
+
+namespace {
+
+template <typename... A>
+fgs_status fail(fgs_status s, const char* fmt, A... args) {
+    return fgs::set_error(s, fmt, args...);
 }
 
 constexpr uint32_t kStateMagic = 0x53534746u;  // "FGSS"
@@ -63,31 +73,7 @@ int64_t streaming_threshold() {
 
 }  // namespace
 
-struct fgs_model {
-    fgs_algo algo;
-    int32_t H, W, npix;
-    fgs_gmm_params gp;
-    fgs_pbas_params pp;
-    GmmConsts gc;
-    PbasConsts pc;
-    int device;
-    hipStream_t stream;
-    bool own_stream;
-    uint8_t* dev;      // one allocation: state + scratch planes + mask
-    size_t dev_bytes;
-    float4* gmm_state;
-    PbasPlanes pb;
-    uint8_t* mask;
-    // host-frame staging (allocated on the first host push)
-    uint8_t* host_stage;
-    uint8_t* dev_in;
-    hipEvent_t stage_done;
-    bool stage_busy;
-    int64_t t;          // frames pushed
-    bool pending;       // PBAS: intents of frame t-1 not yet applied
-    bool poisoned;
-    int32_t cache_policy;  // fgs_cache_policy
-};
+
 
 namespace {
 
@@ -163,12 +149,50 @@ fgs_status ensure_staging(fgs_model* m) {
     return FGS_OK;
 }
 
-bool use_streaming(const fgs_model* m) {
+}  // namespace
+
+bool fgs::model_use_streaming(const fgs_model* m) {
     if (m->cache_policy == FGS_CACHE_STREAM) return true;
     if (m->cache_policy == FGS_CACHE_KEEP) return false;
     const int d = m->device >= 0 && m->device < kMaxDevices ? m->device : 0;
     return g_resident[d].load(std::memory_order_relaxed) > streaming_threshold();
 }
+
+void fgs::model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rs, const uint8_t* depth, int64_t ds,
+                         GmmStepArgs* a) {
+    a->state = m->gmm_state;
+    a->mask = m->mask;
+    a->rgb = rgb;
+    a->depth = depth;
+    a->rgb_stride = rs;
+    a->depth_stride = ds;
+    a->H = m->H;
+    a->W = m->W;
+    a->npix = m->npix;
+    a->streaming = model_use_streaming(m) ? 1 : 0;
+    a->c = m->gc;
+    m->t += 1;
+}
+
+void fgs::model_next_pbas(fgs_model* m, const uint8_t* rgb, int64_t rs, const uint8_t* depth, int64_t ds,
+                          PbasStepArgs* a) {
+    a->m = m->pb;
+    a->rgb = rgb;
+    a->depth = depth;
+    a->rgb_stride = rs;
+    a->depth_stride = ds;
+    a->H = m->H;
+    a->W = m->W;
+    a->npix = m->npix;
+    a->t = (uint32_t)m->t;
+    a->apply_pending = m->pending ? 1 : 0;
+    a->streaming = model_use_streaming(m) ? 1 : 0;
+    a->c = m->pc;
+    m->pending = m->t >= m->pp.N;
+    m->t += 1;
+}
+
+namespace {
 
 fgs_status flush_pending(fgs_model* m) {
     if (m->algo != FGS_PBAS || !m->pending) return FGS_OK;
@@ -409,36 +433,13 @@ fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
 
     if (m->algo == FGS_GMM) {
         GmmStepArgs a;
-        a.state = m->gmm_state;
-        a.mask = m->mask;
-        a.rgb = drgb;
-        a.depth = ddep;
-        a.rgb_stride = rs;
-        a.depth_stride = ds;
-        a.H = m->H;
-        a.W = m->W;
-        a.npix = m->npix;
-        a.streaming = use_streaming(m) ? 1 : 0;
-        a.c = m->gc;
+        model_next_gmm(m, drgb, rs, ddep, ds, &a);
         FGS_HIP(m, gmm_launch_step(a, m->gp.Kc, m->gp.Kd, m->stream));
     } else {
         PbasStepArgs a;
-        a.m = m->pb;
-        a.rgb = drgb;
-        a.depth = ddep;
-        a.rgb_stride = rs;
-        a.depth_stride = ds;
-        a.H = m->H;
-        a.W = m->W;
-        a.npix = m->npix;
-        a.t = (uint32_t)m->t;
-        a.apply_pending = m->pending ? 1 : 0;
-        a.streaming = use_streaming(m) ? 1 : 0;
-        a.c = m->pc;
+        model_next_pbas(m, drgb, rs, ddep, ds, &a);
         FGS_HIP(m, pbas_launch_step(a, m->stream));
-        m->pending = m->t >= m->pp.N;
     }
-    m->t += 1;
     return FGS_OK;
 }
 

@@ -56,6 +56,14 @@ class fgs_pbas_params(ctypes.Structure):
                 ("seed", c_uint64)]
 
 
+class fgs_server_stats(ctypes.Structure):
+    _fields_ = [("struct_size", c_uint32), ("streams_open", c_int32), ("frames_done", c_int64),
+                ("batches", c_int64), ("mean_batch_frames", ctypes.c_double),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("max_latency_s", ctypes.c_double), ("mpix_frames_per_s", ctypes.c_double),
+                ("device_bytes_used", c_uint64), ("device_budget", c_uint64)]
+
+
 _lib = None
 
 
@@ -92,6 +100,15 @@ def _load():
         "fgs_gmm_window_backward": (S, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
         "fgs_gmm_window_records": (S, [c_void_p, c_void_p, c_int32]),
         "fgs_gmm_window_destroy": (S, [c_void_p]),
+        "fgs_server_now": (ctypes.c_double, []),
+        "fgs_server_create": (S, [c_size_t, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+        "fgs_server_open": (S, [c_void_p, c_int32, c_int32, c_int32, c_void_p, POINTER(c_int32)]),
+        "fgs_server_submit": (S, [c_void_p, c_int32, c_void_p, c_void_p, ctypes.c_double, POINTER(c_uint64)]),
+        "fgs_server_wait": (S, [c_void_p, c_uint64, c_void_p, POINTER(ctypes.c_double), c_int32]),
+        "fgs_server_close": (S, [c_void_p, c_int32]),
+        "fgs_server_get_stats": (S, [c_void_p, POINTER(fgs_server_stats)]),
+        "fgs_server_reset_stats": (S, [c_void_p]),
+        "fgs_server_destroy": (S, [c_void_p]),
         "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
         "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
     }
@@ -228,6 +245,55 @@ def fgs_gmm_window_records(w: int, out: int, where: int) -> None:
 
 def fgs_gmm_window_destroy(w: int) -> None:
     _check(_load().fgs_gmm_window_destroy(c_void_p(w)))
+
+
+def fgs_server_now() -> float:
+    return _load().fgs_server_now()
+
+
+def fgs_server_create(hbm_budget_bytes: int, max_streams: int, gmm_K: int = 5, pbas_N_max: int = 24) -> int:
+    out = c_void_p()
+    _check(_load().fgs_server_create(hbm_budget_bytes, max_streams, gmm_K, pbas_N_max, byref(out)))
+    return out.value
+
+
+def fgs_server_open(srv: int, algo: int, H: int, W: int, params=None) -> int:
+    out = c_int32()
+    pp = ctypes.cast(byref(params), c_void_p) if params is not None else None
+    _check(_load().fgs_server_open(c_void_p(srv), algo, H, W, pp, byref(out)))
+    return out.value
+
+
+def fgs_server_submit(srv: int, stream_id: int, rgb: int, depth: int, t_arrival_s: float = 0.0) -> int:
+    out = c_uint64()
+    _check(_load().fgs_server_submit(c_void_p(srv), stream_id, c_void_p(rgb), c_void_p(depth), t_arrival_s,
+                                     byref(out)))
+    return out.value
+
+
+def fgs_server_wait(srv: int, ticket: int, mask: int | None = None, timeout_ms: int = -1) -> float:
+    lat = ctypes.c_double()
+    _check(_load().fgs_server_wait(c_void_p(srv), ticket, c_void_p(mask or 0), byref(lat), timeout_ms))
+    return lat.value
+
+
+def fgs_server_close(srv: int, stream_id: int) -> None:
+    _check(_load().fgs_server_close(c_void_p(srv), stream_id))
+
+
+def fgs_server_get_stats(srv: int) -> dict:
+    st = fgs_server_stats()
+    st.struct_size = ctypes.sizeof(fgs_server_stats)
+    _check(_load().fgs_server_get_stats(c_void_p(srv), byref(st)))
+    return {k: getattr(st, k) for k, _ in fgs_server_stats._fields_ if k != "struct_size"}
+
+
+def fgs_server_reset_stats(srv: int) -> None:
+    _check(_load().fgs_server_reset_stats(c_void_p(srv)))
+
+
+def fgs_server_destroy(srv: int) -> None:
+    _check(_load().fgs_server_destroy(c_void_p(srv)))
 
 
 def fgs_philox4x32_10(seed: int, ctr: int, out: int, n: int, hip_stream: int | None = None) -> None:

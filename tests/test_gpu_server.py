@@ -1,0 +1,177 @@
+"""Multi-stream server: every stream's masks in the batched mix are identical to the same
+stream driven alone through fgs_push_frame; admission by HBM budget; back-pressure; close
+with frames queued; the 32-stream, 30 fps mixed-resolution workload within one frame
+period at p99."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from gpu_util import log  # noqa: E402
+from synth import Scene, preset  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2002_00250_amd import fgs
+    fgs.lib()
+    yield
+
+
+def _params(algo, K=5, N=20, seed=None):
+    from paper_2002_00250_amd import fgs
+    if algo == fgs.FGS_GMM:
+        p = fgs.fgs_gmm_params_default()
+        p.Kc = p.Kd = K
+    else:
+        p = fgs.fgs_pbas_params_default()
+        p.N = N
+        if seed is not None:
+            p.seed = seed
+    return p
+
+
+def _frames(H, W, n, seed):
+    sc = Scene(preset("pbas_640x480", H=H, W=W, seed=seed))
+    return [sc.frame(t)[:2] for t in range(n)]
+
+
+def _alone(algo, H, W, params, frames):
+    from paper_2002_00250_amd import fgs
+    m = fgs.Model(algo, H, W, params)
+    out = []
+    for rgb, dep in frames:
+        m.push(rgb, dep)
+        out.append(m.mask_host())
+    m.close()
+    return out
+
+
+def test_mix_equals_alone():
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    specs = [(fgs.FGS_GMM, 48, 64), (fgs.FGS_PBAS, 48, 64), (fgs.FGS_GMM, 70, 100),
+             (fgs.FGS_PBAS, 70, 100), (fgs.FGS_GMM, 120, 160), (fgs.FGS_PBAS, 121, 159),
+             (fgs.FGS_PBAS, 5, 7)]
+    T = 36
+    srv = Server(1 << 30, 16, gmm_K=5, pbas_N_max=24)
+    streams = []
+    for i, (algo, H, W) in enumerate(specs):
+        p = _params(algo, seed=1000 + i)
+        streams.append((srv.open(algo, H, W, p), algo, H, W, p, _frames(H, W, T, seed=50 + i)))
+    got = {sid: [] for sid, *_ in streams}
+    for t in range(T):
+        tickets = []
+        for sid, algo, H, W, p, fr in streams:
+            if (t + sid) % 3 == 0 and t > 0:      # uneven arrivals: batches of different make-up
+                continue
+            tickets.append((sid, srv.submit(sid, *fr[t]), H, W))
+        for sid, tk, H, W in tickets:
+            m = np.empty((H, W), np.uint8)
+            srv.wait(tk, m)
+            got[sid].append(m)
+        for sid, algo, H, W, p, fr in streams:   # the skipped ones now
+            if (t + sid) % 3 == 0 and t > 0:
+                m = np.empty((H, W), np.uint8)
+                srv.wait(srv.submit(sid, *fr[t]), m)
+                got[sid].append(m)
+    st = srv.stats()
+    log(f"server mix: {st['frames_done']} frames in {st['batches']} batches "
+        f"({st['mean_batch_frames']:.2f} per batch)")
+    for sid, algo, H, W, p, fr in streams:
+        ref = _alone(algo, H, W, p, fr)
+        diff = sum(int((a != b).sum()) for a, b in zip(got[sid], ref))
+        log(f"stream {sid} ({'GMM' if algo == fgs.FGS_GMM else 'PBAS'} {H}x{W}): {diff} mask pixels differ from alone")
+        assert diff == 0
+    srv.destroy()
+
+
+def test_admission_by_budget_and_close():
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    srv = Server(64 << 20, 8, gmm_K=5, pbas_N_max=24)
+    ids = []
+    with pytest.raises(fgs.FgsError) as e:
+        for _ in range(10):
+            ids.append(srv.open(fgs.FGS_GMM, 240, 320, _params(fgs.FGS_GMM)))
+    assert e.value.status == fgs.FGS_ERR_BUSY and len(ids) >= 1
+    used = srv.stats()["device_bytes_used"]
+    assert used <= 64 << 20
+    srv.close_stream(ids[0])
+    assert srv.stats()["device_bytes_used"] < used
+    ids[0] = srv.open(fgs.FGS_GMM, 240, 320, _params(fgs.FGS_GMM))   # admitted again
+    with pytest.raises(fgs.FgsError) as e:
+        srv.open(fgs.FGS_GMM, 24, 32, _params(fgs.FGS_GMM, K=3))     # wrong K class
+    assert e.value.status == fgs.FGS_ERR_UNSUPPORTED
+    srv.destroy()
+
+
+def test_backpressure_and_close_with_frames_queued():
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    srv = Server(1 << 30, 4)
+    sid = srv.open(fgs.FGS_PBAS, 64, 96, _params(fgs.FGS_PBAS))
+    fr = _frames(64, 96, 6, seed=3)
+    tickets = [srv.submit(sid, *fr[i]) for i in range(4)]
+    with pytest.raises(fgs.FgsError) as e:
+        srv.submit(sid, *fr[4])                     # ring of 4 full until collected
+    assert e.value.status == fgs.FGS_ERR_BUSY
+    srv.wait(tickets[0])
+    t5 = srv.submit(sid, *fr[4])
+    srv.close_stream(sid)
+    outcomes = []
+    for tk in tickets[1:] + [t5]:
+        try:
+            srv.wait(tk, timeout_ms=10000)
+            outcomes.append("done")
+        except fgs.FgsError as err:
+            assert err.status == fgs.FGS_ERR_BAD_STATE
+            outcomes.append("dropped")
+    log(f"close with frames queued: {outcomes}")
+    with pytest.raises(fgs.FgsError):
+        srv.submit(sid, *fr[5])
+    srv.destroy()
+
+
+def test_32_streams_30fps_mixed_resolution():
+    # 12x 424x240, 12x 640x480, 8x 1280x720; even streams GMM K=5, odd PBAS N=20;
+    # frames at 30 fps, random phase, +-5 ms jitter.  p99 latency below one frame period,
+    # and three streams' masks identical to the same streams alone.
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server, StreamLoad, run_camera_load
+    sizes = [(240, 424)] * 12 + [(480, 640)] * 12 + [(720, 1280)] * 8
+    srv = Server(64 << 30, 32, gmm_K=5, pbas_N_max=24)
+    loads, meta = [], []
+    for i, (H, W) in enumerate(sizes):
+        algo = fgs.FGS_GMM if i % 2 == 0 else fgs.FGS_PBAS
+        p = _params(algo, seed=7000 + i)
+        sid = srv.open(algo, H, W, p)
+        fr = _frames(H, W, 4, seed=300 + i)
+        keep = i in (0, 13, 31)
+        loads.append(StreamLoad(sid, fr, keep_masks=keep))
+        meta.append((algo, H, W, p))
+    warm = [StreamLoad(ld.sid, ld.frames) for ld in loads]
+    run_camera_load(srv, warm, duration_s=1.0, seed=1)       # PBAS fills its samples
+    srv.reset_stats()
+    lat, wall = run_camera_load(srv, loads, duration_s=3.0, seed=2)
+    st = srv.stats()
+    p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+    offered = sum(H * W for H, W in sizes) * 30 / 1e6
+    log(f"32 streams @30fps: {lat.size} frames, p50 {p50 * 1e3:.2f} ms, p99 {p99 * 1e3:.2f} ms, "
+        f"max {lat.max() * 1e3:.2f} ms; {st['mean_batch_frames']:.2f} frames/batch; "
+        f"{st['mpix_frames_per_s']:.1f} Mpx-f/s served (offered {offered:.1f})")
+    assert p99 < 1.0 / 30
+    # masks of three streams equal the same frames pushed alone (warm-up frames first)
+    for i in (0, 13, 31):
+        algo, H, W, p = meta[i]
+        seq = [loads[i].frames[k % 4] for k in range(len(warm[i].latencies))] + \
+              [loads[i].frames[k % 4] for k in range(len(loads[i].latencies))]
+        ref = _alone(algo, H, W, p, seq)[len(warm[i].latencies):]
+        got = [m for _, m in sorted(loads[i].masks, key=lambda x: x[0])]
+        diff = sum(int((a != b).sum()) for a, b in zip(got, ref))
+        log(f"stream {i}: {diff} mask pixels differ from alone over {len(got)} frames")
+        assert len(got) == len(ref) and diff == 0
+    srv.destroy()
