@@ -55,10 +55,13 @@ def measured_traffic(kernel_file: str):
     if not os.path.exists(path):
         return None
     kv = _kv(path)
-    src = os.path.join(ROOT, kv.get("source", ""))
-    if not os.path.isfile(src):
-        return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("source_sha256_16"):
+    h = hashlib.sha256()
+    for src in kv.get("sources", "").split():
+        full = os.path.join(ROOT, src)
+        if not os.path.isfile(full):
+            return None
+        h.update(open(full, "rb").read())
+    if h.hexdigest()[:16] != kv.get("sources_sha256_16"):
         return None
     return float(kv["hbm_bytes_per_dispatch"])
 
@@ -108,6 +111,145 @@ def cpu_baseline(rgb, depth):
                        f"N=35 updating frames ({tp:.1f} s), one host thread; step = one GMM + one PBAS frame")
 
 
+def serving_main(args):
+    """The 32-stream serving workload: 12x 424x240, 12x 640x480, 8x 1280x720, even streams
+    GMM K=5, odd PBAS N=20, frames at 30 fps (random phase, +-5 ms jitter); then the same
+    streams at saturation (every ring kept full) for the aggregate capacity."""
+    import threading
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server, StreamLoad, run_camera_load
+    from synth import Scene, preset
+    sizes = [(240, 424)] * 12 + [(480, 640)] * 12 + [(720, 1280)] * 8
+    srv = Server(64 << 30, 32, gmm_K=5, pbas_N_max=24)
+    loads = []
+    for i, (h, w) in enumerate(sizes):
+        if i % 2 == 0:
+            p = fgs.fgs_gmm_params_default()
+            p.Kc = p.Kd = 5
+            algo = fgs.FGS_GMM
+        else:
+            p = fgs.fgs_pbas_params_default()
+            p.N = 20
+            p.seed = 7000 + i
+            algo = fgs.FGS_PBAS
+        sid = srv.open(algo, h, w, p)
+        sc = Scene(preset("hd_1280x720", H=h, W=w, seed=300 + i))
+        loads.append(StreamLoad(sid, [sc.frame(t)[:2] for t in range(4)]))
+    run_camera_load(srv, [StreamLoad(l.sid, l.frames) for l in loads], duration_s=1.0, seed=1)
+    srv.reset_stats()
+    lat, wall = run_camera_load(srv, loads, duration_s=args.serve_seconds, seed=2)
+    st = srv.stats()
+    offered = sum(h * w for h, w in sizes) * 30 / 1e6
+
+    # saturation: one thread per stream keeps its ring full for the same duration
+    srv.reset_stats()
+    stop = [False]
+
+    def pump(ld):
+        tickets, k = [], 0
+        while not stop[0]:
+            rgb, dep = ld.frames[k % len(ld.frames)]
+            try:
+                tickets.append(srv.submit(ld.sid, rgb, dep))
+                k += 1
+            except fgs.FgsError:
+                srv.wait(tickets.pop(0))
+        for t in tickets:
+            srv.wait(t)
+    ths = [threading.Thread(target=pump, args=(ld,)) for ld in loads]
+    for t in ths:
+        t.start()
+    time.sleep(args.serve_seconds)
+    stop[0] = True
+    for t in ths:
+        t.join()
+    sat = srv.stats()
+    srv.destroy()
+    out = {
+        "metric": "p99 frame latency (32 mixed-resolution RGB-D streams at 30 fps)",
+        "value": round(float(np.percentile(lat, 99)) * 1e3, 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "frames": int(lat.size),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+        "max_ms": round(float(lat.max()) * 1e3, 4),
+        "frame_period_ms": round(1000 / 30, 3),
+        "served_Mpx_frames_per_s": round(st["mpix_frames_per_s"], 2),
+        "offered_Mpx_frames_per_s": round(offered, 2),
+        "frames_per_batch": round(st["mean_batch_frames"], 3),
+        "saturated": {"Mpx_frames_per_s": round(sat["mpix_frames_per_s"], 1),
+                      "frames_per_batch": round(sat["mean_batch_frames"], 2),
+                      "p50_ms": round(sat["p50_latency_s"] * 1e3, 3),
+                      "p99_ms": round(sat["p99_latency_s"] * 1e3, 3)},
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "32 streams: 12x 424x240, 12x 640x480, 8x 1280x720; even GMM K=5, odd PBAS N=20; "
+                               "30 fps, +-5 ms jitter", "seconds": args.serve_seconds},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_main(args):
+    """GMM adjoint on the 640x480, K=3, 64-frame window (checkpoint every 16 frames): time of
+    one forward + backward (one Adam step of theta = (alpha, lambda, w_d))."""
+    import torch
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.adjoint import GmmWindow, GmmWindowFunction, window_bce_loss
+    from synth import Scene, preset
+    T, Hh, Ww = 64, 480, 640
+    rgb, dep, gt = Scene(preset("adjoint_640x480")).frames(0, T)
+    r = torch.from_numpy(rgb).cuda()
+    d = torch.from_numpy(dep.view(np.int16)).cuda()
+    g = torch.from_numpy(gt).cuda()
+    p = fgs.fgs_gmm_params_default()
+    win = GmmWindow(T, Hh, Ww, p, checkpoint_every=16)
+    theta = torch.tensor([0.01, 2.5, 1.0], device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([theta], lr=1e-3)
+
+    def step():
+        opt.zero_grad()
+        Z, has = GmmWindowFunction.apply(theta, r, d, win)
+        loss = window_bce_loss(Z, has, g)
+        loss.backward()
+        opt.step()
+        with torch.no_grad():   # keep theta in its valid range
+            theta.clamp_(min=torch.tensor([1e-4, 0.5, 0.0], device="cuda"),
+                         max=torch.tensor([0.5, 10.0, 10.0], device="cuda"))
+        return loss
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    steps = max(5, args.steps // 10)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    tf = tb = 0.0
+    for _ in range(steps):
+        e[0].record()
+        Z, has = win.forward(theta.detach(), r, d)
+        e[1].record()
+        win.backward(theta.detach(), r, d, torch.zeros_like(Z))
+        e[2].record()
+        torch.cuda.synchronize()
+        tf += e[0].elapsed_time(e[1])
+        tb += e[1].elapsed_time(e[2])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss = step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    px = T * Hh * Ww
+    out = {"metric": "GMM adjoint window step (forward + backward + Adam)", "value": round(wall * 1e3, 3),
+           "unit": "ms", "higher_is_better": False, "n_gpus": 1, "steps": steps,
+           "forward_ms": round(tf / steps, 3), "backward_ms": round(tb / steps, 3),
+           "forward_Mpx_frames_per_s": round(px / (tf / steps * 1e-3) / 1e6, 1),
+           "backward_Mpx_frames_per_s": round(px / (tb / steps * 1e-3) / 1e6, 1),
+           "loss": round(float(loss), 5), "theta": [round(float(x), 6) for x in theta.detach().cpu()],
+           "dtype": "f32 (fp64 gradient reduction)", "data": "synthetic",
+           "config": {"workload": "640x480, K=3, 64-frame window, checkpoint every 16 frames, BCE on sigmoid(Z)"}}
+    win.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +258,9 @@ def main():
     ap.add_argument("--frames", type=int, default=64, help="distinct pre-staged frames (cycled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--serving", action="store_true", help="run the 32-stream serving workload instead")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--adjoint", action="store_true", help="time the GMM adjoint window step instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -130,6 +275,12 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     fgs.lib()
+    if args.serving:
+        serving_main(args)
+        return
+    if args.adjoint:
+        adjoint_main(args)
+        return
 
     # A dedicated stream (the legacy null stream has handle 0, which the library reads as
     # "create a private stream"); every launch and every timing event goes on it.
