@@ -165,6 +165,19 @@ fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
                           const uint16_t* depth, int64_t depth_stride, fgs_mem where);
 
 /*
+ * As fgs_push_frame, for a depth map of depth_H x depth_W pixels (depth_stride
+ * bytes per row) taken at another resolution than the RGB frame: the kernel
+ * brings it to the RGB grid by nearest-neighbour upscaling on pixel centres,
+ * depth(x, y) = D[floor((y + 1/2) depth_H / H)][floor((x + 1/2) depth_W / W)]
+ * (Sec. 4.3: depth is upscaled to the RGB resolution when they differ, e.g.
+ * 1280x720 RGB with 848x480 depth).  With FGS_MEM_HOST the depth map may not
+ * have more pixels than the RGB frame.  Errors as fgs_push_frame.
+ */
+fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
+                                 const uint16_t* depth, int64_t depth_stride, int32_t depth_H,
+                                 int32_t depth_W, fgs_mem where);
+
+/*
  * Copy the mask of the most recent frame into `mask` (H rows of W bytes,
  * `stride` bytes apart).  FGS_MEM_HOST waits for the frame to finish;
  * FGS_MEM_DEVICE enqueues a device copy on the model's stream.

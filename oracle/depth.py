@@ -38,3 +38,14 @@ def depth_q8(depth, depth_max_mm: int = DEPTH_MAX_MM) -> np.ndarray:
 def depth_valid(depth) -> np.ndarray:
     """Depth is used only where the sensor reports a value greater than 0 (Sec. 3.1, 3.2)."""
     return np.asarray(depth) > 0
+
+
+def upscale_nearest(depth, H: int, W: int) -> np.ndarray:
+    """Depth map brought to an H x W grid by nearest neighbour on pixel centres (Sec. 4.3:
+    depth is upscaled to the RGB resolution when they differ):
+    out[y, x] = depth[floor((y + 1/2) Hd / H), floor((x + 1/2) Wd / W)]."""
+    d = np.asarray(depth)
+    Hd, Wd = d.shape
+    ys = ((2 * np.arange(H, dtype=np.int64) + 1) * Hd) // (2 * H)
+    xs = ((2 * np.arange(W, dtype=np.int64) + 1) * Wd) // (2 * W)
+    return d[ys][:, xs]

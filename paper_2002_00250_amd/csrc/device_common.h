@@ -15,6 +15,20 @@ __device__ __forceinline__ uint32_t depth_code(uint32_t d_mm, uint32_t full_scal
     return q > 255u ? 255u : q;
 }
 
+// Depth (mm) seen by RGB pixel (x, y).  The depth map is either W x H, or dw x dh
+// and brought to the RGB grid by nearest-neighbour upscaling on pixel centres
+// (Sec. 4.3: depth is upscaled to the RGB resolution when the two differ):
+// xd = floor((x + 1/2) dw / W), yd = floor((y + 1/2) dh / H).
+__device__ __forceinline__ uint32_t load_depth(const uint8_t* depth, int64_t stride, int x, int y,
+                                               int W, int H, int dw, int dh) {
+    int xd = x, yd = y;
+    if (dw > 0) {
+        xd = (int)(((int64_t)(2 * x + 1) * dw) / (2 * (int64_t)W));
+        yd = (int)(((int64_t)(2 * y + 1) * dh) / (2 * (int64_t)H));
+    }
+    return *reinterpret_cast<const uint16_t*>(depth + (int64_t)yd * stride + 2 * xd);
+}
+
 struct U32x4 {
     uint32_t v[4];
 };

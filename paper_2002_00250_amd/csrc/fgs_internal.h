@@ -33,6 +33,7 @@ struct GmmStepArgs {
     const uint8_t* depth;  // uint16 rows, addressed in bytes
     int64_t rgb_stride, depth_stride;
     int32_t H, W, npix;
+    int32_t depth_h, depth_w;  // 0: depth is H x W; else its size, upscaled to H x W
     GmmConsts c;
 };
 
@@ -99,6 +100,7 @@ struct PbasStepArgs {
     const uint8_t* depth;
     int64_t rgb_stride, depth_stride;
     int32_t H, W, npix;
+    int32_t depth_h, depth_w;  // 0: depth is H x W; else its size, upscaled to H x W
     uint32_t t;            // frame index
     int32_t apply_pending; // intents of frame t-1 still to be applied
     int32_t streaming;     // 1: non-temporal sample traffic (working set beyond the last-level cache)

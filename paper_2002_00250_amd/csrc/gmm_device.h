@@ -207,7 +207,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     const int x = p - y * a.W;
 
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
-    const uint32_t dmm = *reinterpret_cast<const uint16_t*>(a.depth + (int64_t)y * a.depth_stride + 2 * x);
+    const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
     const float Xc[3] = {(float)px[0], (float)px[1], (float)px[2]};
     const bool valid = dmm > 0u;
     const float Xd[1] = {(float)depth_code(dmm, a.c.depth_max_mm)};

@@ -41,9 +41,10 @@ fgs_status set_error(fgs_status s, const char* fmt, ...);
 bool model_use_streaming(const fgs_model* m);
 // Launch arguments of the model's next frame read from device frames; advances the
 // model's frame counter and pending-intent flag exactly as a push does.
+// depth_h = depth_w = 0: the depth map has the model's size.
 void model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
-                    int64_t depth_stride, GmmStepArgs* a);
+                    int64_t depth_stride, int32_t depth_h, int32_t depth_w, GmmStepArgs* a);
 void model_next_pbas(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
-                     int64_t depth_stride, PbasStepArgs* a);
+                     int64_t depth_stride, int32_t depth_h, int32_t depth_w, PbasStepArgs* a);
 
 }  // namespace fgs

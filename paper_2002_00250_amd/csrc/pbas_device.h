@@ -153,7 +153,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 
     // Ingest.
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
-    const uint32_t dmm = *reinterpret_cast<const uint16_t*>(a.depth + (int64_t)y * a.depth_stride + 2 * x);
+    const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
     const bool valid = dmm > 0u;
     int I[4];
     I[0] = px[0];
@@ -307,7 +307,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 __device__ __forceinline__ void fill_pixel(const PbasStepArgs& a, int p) {
     const int y = p / a.W, x = p - (p / a.W) * a.W;
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
-    const uint32_t dmm = *reinterpret_cast<const uint16_t*>(a.depth + (int64_t)y * a.depth_stride + 2 * x);
+    const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
     const uint32_t Iw = (uint32_t)px[0] | ((uint32_t)px[1] << 8) | ((uint32_t)px[2] << 16) |
                         (depth_code(dmm, a.c.depth_max_mm) << 24);
     a.m.samples[(int64_t)a.t * a.npix + p] = Iw;

@@ -159,7 +159,9 @@ bool fgs::model_use_streaming(const fgs_model* m) {
 }
 
 void fgs::model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rs, const uint8_t* depth, int64_t ds,
-                         GmmStepArgs* a) {
+                         int32_t dh, int32_t dw, GmmStepArgs* a) {
+    a->depth_h = dh;
+    a->depth_w = dw;
     a->state = m->gmm_state;
     a->mask = m->mask;
     a->rgb = rgb;
@@ -175,7 +177,9 @@ void fgs::model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rs, const uin
 }
 
 void fgs::model_next_pbas(fgs_model* m, const uint8_t* rgb, int64_t rs, const uint8_t* depth, int64_t ds,
-                          PbasStepArgs* a) {
+                          int32_t dh, int32_t dw, PbasStepArgs* a) {
+    a->depth_h = dh;
+    a->depth_w = dw;
     a->m = m->pb;
     a->rgb = rgb;
     a->depth = depth;
@@ -396,12 +400,24 @@ fgs_status fgs_destroy(fgs_model* m) {
 fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
                           const uint16_t* depth, int64_t depth_stride, fgs_mem where) {
     if (!m) return fail(FGS_ERR_INVALID_ARG, "model is NULL");
+    return fgs_push_frame_scaled(m, rgb, rgb_stride, depth, depth_stride, m->H, m->W, where);
+}
+
+fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
+                                 const uint16_t* depth, int64_t depth_stride, int32_t depth_H,
+                                 int32_t depth_W, fgs_mem where) {
+    if (!m) return fail(FGS_ERR_INVALID_ARG, "model is NULL");
     if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
     if (!rgb || !depth) return fail(FGS_ERR_INVALID_ARG, "frame pointer is NULL");
-    if (rgb_stride < 3 * (int64_t)m->W || depth_stride < 2 * (int64_t)m->W || (depth_stride & 1) ||
+    if (depth_H < 1 || depth_W < 1 || (int64_t)depth_H * depth_W > kMaxPixels)
+        return fail(FGS_ERR_INVALID_ARG, "bad depth size %d x %d", depth_H, depth_W);
+    if (where == FGS_MEM_HOST && (int64_t)depth_H * depth_W > (int64_t)m->npix)
+        return fail(FGS_ERR_INVALID_ARG, "host depth maps may not have more pixels than the RGB frame");
+    if (rgb_stride < 3 * (int64_t)m->W || depth_stride < 2 * (int64_t)depth_W || (depth_stride & 1) ||
         ((uintptr_t)depth & 1))
-        return fail(FGS_ERR_INVALID_ARG, "bad stride (rgb %lld, depth %lld) for W = %d",
-                    (long long)rgb_stride, (long long)depth_stride, m->W);
+        return fail(FGS_ERR_INVALID_ARG, "bad stride (rgb %lld, depth %lld) for W = %d, depth W = %d",
+                    (long long)rgb_stride, (long long)depth_stride, m->W, depth_W);
+    const bool scaled = depth_H != m->H || depth_W != m->W;
     if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
         return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
     if (m->t >= 0xFFFFFFFFll) return fail(FGS_ERR_BAD_STATE, "frame counter exhausted");
@@ -416,11 +432,11 @@ fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
         const size_t rgb_bytes = (size_t)m->npix * 3;
         uint8_t* hr = m->host_stage;
         uint8_t* hd = m->host_stage + align256(rgb_bytes);
-        for (int y = 0; y < m->H; ++y) {
+        for (int y = 0; y < m->H; ++y)
             std::memcpy(hr + (size_t)y * 3 * m->W, rgb + (size_t)y * rgb_stride, (size_t)3 * m->W);
-            std::memcpy(hd + (size_t)y * 2 * m->W, reinterpret_cast<const uint8_t*>(depth) + (size_t)y * depth_stride,
-                        (size_t)2 * m->W);
-        }
+        for (int y = 0; y < depth_H; ++y)
+            std::memcpy(hd + (size_t)y * 2 * depth_W, reinterpret_cast<const uint8_t*>(depth) + (size_t)y * depth_stride,
+                        (size_t)2 * depth_W);
         const size_t bytes = align256(rgb_bytes) + (size_t)m->npix * 2;
         FGS_HIP(m, hipMemcpyAsync(m->dev_in, m->host_stage, bytes, hipMemcpyHostToDevice, m->stream));
         FGS_HIP(m, hipEventRecord(m->stage_done, m->stream));
@@ -428,16 +444,17 @@ fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
         drgb = m->dev_in;
         ddep = m->dev_in + align256(rgb_bytes);
         rs = 3 * (int64_t)m->W;
-        ds = 2 * (int64_t)m->W;
+        ds = 2 * (int64_t)depth_W;
     }
+    const int32_t dh = scaled ? depth_H : 0, dw = scaled ? depth_W : 0;
 
     if (m->algo == FGS_GMM) {
         GmmStepArgs a;
-        model_next_gmm(m, drgb, rs, ddep, ds, &a);
+        model_next_gmm(m, drgb, rs, ddep, ds, dh, dw, &a);
         FGS_HIP(m, gmm_launch_step(a, m->gp.Kc, m->gp.Kd, m->stream));
     } else {
         PbasStepArgs a;
-        model_next_pbas(m, drgb, rs, ddep, ds, &a);
+        model_next_pbas(m, drgb, rs, ddep, ds, dh, dw, &a);
         FGS_HIP(m, pbas_launch_step(a, m->stream));
     }
     return FGS_OK;

@@ -158,12 +158,12 @@ hipError_t issue(fgs_server* s, Batch* b) {
         const uint8_t* drgb = sl.d_in;
         const uint8_t* ddep = sl.d_in + st->rgb_bytes;
         if (st->algo == FGS_GMM) {
-            model_next_gmm(st->model, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, &en.g);
+            model_next_gmm(st->model, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &en.g);
             en.ntiles = (st->npix + 255) / 256;
             streaming = streaming || en.g.streaming;
         } else {
             en.fill = st->model->t < st->model->pp.N ? 1 : 0;
-            model_next_pbas(st->model, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, &en.p);
+            model_next_pbas(st->model, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &en.p);
             en.tiles_x = (st->W + 63) / 64;
             en.ntiles = en.fill ? (st->npix + 255) / 256 : en.tiles_x * ((st->H + 3) / 4);
             streaming = streaming || en.p.streaming;

@@ -84,6 +84,7 @@ def _load():
         "fgs_create": (S, [c_int32, c_int32, c_int32, c_void_p, c_void_p, POINTER(c_void_p)]),
         "fgs_destroy": (S, [c_void_p]),
         "fgs_push_frame": (S, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32]),
+        "fgs_push_frame_scaled": (S, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32, c_int32]),
         "fgs_get_mask": (S, [c_void_p, c_void_p, c_int64, c_int32]),
         "fgs_mask_device_ptr": (S, [c_void_p, POINTER(c_void_p)]),
         "fgs_state_size": (S, [c_void_p, POINTER(c_size_t)]),
@@ -169,6 +170,12 @@ def fgs_destroy(m: int) -> None:
 def fgs_push_frame(m: int, rgb: int, rgb_stride: int, depth: int, depth_stride: int, where: int) -> None:
     _check(_load().fgs_push_frame(c_void_p(m), c_void_p(rgb), rgb_stride, c_void_p(depth),
                                   depth_stride, where))
+
+
+def fgs_push_frame_scaled(m: int, rgb: int, rgb_stride: int, depth: int, depth_stride: int, depth_H: int,
+                          depth_W: int, where: int) -> None:
+    _check(_load().fgs_push_frame_scaled(c_void_p(m), c_void_p(rgb), rgb_stride, c_void_p(depth),
+                                         depth_stride, depth_H, depth_W, where))
 
 
 def fgs_get_mask(m: int, mask: int, stride: int, where: int) -> None:
@@ -392,6 +399,7 @@ class Model:
         return x.data_ptr(), (FGS_MEM_DEVICE if x.is_cuda else FGS_MEM_HOST)
 
     def push(self, rgb, depth):
+        """Push one frame; a depth map of another size than rgb is upscaled to it."""
         if isinstance(rgb, np.ndarray):
             rgb = np.ascontiguousarray(rgb, np.uint8)
             depth = np.ascontiguousarray(depth, np.uint16)
@@ -399,8 +407,13 @@ class Model:
         pd, wd = self._ptr_where(depth)
         if wr != wd:
             raise ValueError("rgb and depth must both be host or both be device memory")
-        fgs_push_frame(self.handle, pr, rgb.stride(0) if not isinstance(rgb, np.ndarray) else rgb.strides[0],
-                       pd, (depth.stride(0) * 2) if not isinstance(depth, np.ndarray) else depth.strides[0], wr)
+        rs = rgb.stride(0) if not isinstance(rgb, np.ndarray) else rgb.strides[0]
+        ds = (depth.stride(0) * 2) if not isinstance(depth, np.ndarray) else depth.strides[0]
+        dh, dw = int(depth.shape[0]), int(depth.shape[1])
+        if (dh, dw) == (self.H, self.W):
+            fgs_push_frame(self.handle, pr, rs, pd, ds, wr)
+        else:
+            fgs_push_frame_scaled(self.handle, pr, rs, pd, ds, dh, dw, wr)
 
     def mask_host(self) -> np.ndarray:
         out = np.empty((self.H, self.W), np.uint8)

@@ -40,3 +40,23 @@ def test_other_full_scale():
     # A 65535 mm full scale puts 257 mm in one code (the literal 16-bit -> 8-bit rescale).
     q = depth_q8(np.array([128, 129, 385, 386, 65535], np.uint16), depth_max_mm=65535)
     assert q.tolist() == [1, 1, 1, 2, 255]
+
+
+def test_upscale_nearest_identity_and_integer_factor():
+    from oracle.depth import upscale_nearest
+    rng = np.random.default_rng(1)
+    d = rng.integers(0, 5000, (6, 9)).astype(np.uint16)
+    np.testing.assert_array_equal(upscale_nearest(d, 6, 9), d)
+    up = upscale_nearest(d, 12, 18)            # factor 2: every sample becomes a 2x2 block
+    np.testing.assert_array_equal(up, np.repeat(np.repeat(d, 2, 0), 2, 1))
+
+
+def test_upscale_nearest_centres_for_480_to_720():
+    from oracle.depth import upscale_nearest
+    d = np.arange(480, dtype=np.uint16)[:, None] * np.ones((1, 3), np.uint16)
+    up = upscale_nearest(d, 720, 3)
+    # output row y samples input row floor((y + 1/2) * 480 / 720): 0,1,1,2,3,3,...
+    assert up[:8, 0].tolist() == [0, 1, 1, 2, 3, 3, 4, 5]
+    assert up[-1, 0] == 479
+    counts = np.bincount(up[:, 0], minlength=480)
+    assert set(counts.tolist()) == {1, 2} and counts.sum() == 720
