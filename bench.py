@@ -318,7 +318,7 @@ def main():
     ap.add_argument("--table1", action="store_true", help="time the paper's Table 1 resolutions instead")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(each camera stream is independent: sharding is by stream, one process per GPU)",
               file=sys.stderr)
         sys.exit(2)

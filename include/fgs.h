@@ -50,7 +50,7 @@ typedef enum fgs_status {
     FGS_ERR_DEVICE = 3,        /* a HIP call failed; the model is poisoned */
     FGS_ERR_BAD_STATE = 4,     /* call not valid in the model's current state */
     FGS_ERR_BUSY = 5,          /* resource temporarily unavailable */
-    FGS_ERR_UNSUPPORTED = 6    /* valid request this build does not implement */
+    FGS_ERR_UNSUPPORTED = 6    /* valid request the library does not implement */
 } fgs_status;
 
 typedef enum fgs_algo { FGS_GMM = 1, FGS_PBAS = 2 } fgs_algo;
