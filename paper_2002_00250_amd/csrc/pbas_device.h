@@ -91,61 +91,89 @@ __device__ __forceinline__ void apply_pending(const uint64_t* lds, int lx, int l
     }
 }
 
-// One updating frame.  The pixel's N sample words live in registers between one
-// dense coalesced read and one dense coalesced write of the sample planes (the
-// random slot replacements are applied in registers), so no sample plane sees a
-// partial-line write.  The Philox draws and the 1/T tests do not depend on the
-// classification, so the candidate self-update slots are known first and their
-// D-history bytes are fetched before the samples, off the critical path.
-// Gather the neighbour writes aimed at pixel (lx,ly) into per-channel slot
-// bit-planes: plane j, word w holds slots 32w..32w+31.  Each lane touches only its
-// own words of `pend` (layout [word][lane]), so no atomics and no barrier.
-template <int PW>
-__device__ __forceinline__ void gather_pending(const uint64_t* lds, uint32_t* pend, int lx, int ly,
-                                               int tid, uint32_t lastw, int N) {
-    const bool depth_ok = (lastw >> 24) != 0u;  // y had depth at that frame
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        const int ox = nb_dx(d), oy = nb_dy(d);
-        const uint64_t v = lds[(ly + 1 + oy) * kHaloW + (lx + 1 + ox)];
+// Pending writes into a tile pixel are kept as slot bit-words: for sample slot k
+// of channel j, bit 8*j + (k & 7) of word k >> 3.  Shifting word k >> 3 right by
+// k & 7 and masking with 0x01010101 leaves one bit per channel in the low bit of
+// that channel's byte, which a 16-bit lane multiply by 0xFF widens into a byte
+// mask of the sample word.
+constexpr uint32_t kLowBits = 0x01010101u;
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 h2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t w32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+
+// Byte mask of the channels whose bit is set for slot k in bit-word `word`.
+__device__ __forceinline__ uint32_t slot_byte_mask(uint32_t word, int k) {
+    const uint32_t bits = (word >> (k & 7)) & kLowBits;
+    return w32(h2(bits) * (u16x2){0xFF, 0xFF});
+}
+
+// LDS a tile needs: the pending bit-words, word w of tile pixel i at [w][i].
+template <int NMAX>
+struct PbasLds {
+    static constexpr int NW = (NMAX + 7) / 8;  // bit-words per pixel
+    uint32_t pend[NW * kBlock];
+};
+
+// Frame t-1's neighbour writes aimed at this tile, scattered from their sources:
+// every pixel of the tile and of its 1-pixel halo is read once, and each intent
+// that lands inside the tile sets its (slot, channel) bit in the destination's
+// bit-words with an LDS atomic OR.  Whether the destination had depth at t-1 is
+// checked by the destination.
+template <int NMAX>
+__device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint64_t* intents, int x0,
+                                                int y0, int H, int W, int N) {
+    for (int i = threadIdx.x; i < kHaloW * kHaloH; i += kBlock) {
+        const int hx = i % kHaloW, hy = i / kHaloW;
+        const int gx = x0 + hx - 1, gy = y0 + hy - 1;
+        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
+        const uint64_t v = intents[(int64_t)gy * W + gx];
         if (v == 0) continue;
-        const uint32_t want = 0x8u | (uint32_t)(7 - d);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t f = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
+            const int d = (int)((f >> 12) & 7u);
+            const int tx = hx - 1 + nb_dx(d), ty = hy - 1 + nb_dy(d);
             const int slot = (int)(f & 0x3Fu);
-            if ((f >> 12) != want || slot >= N || (j == 3 && !depth_ok)) continue;
-            pend[(j * PW + (slot >> 5)) * kBlock + tid] |= 1u << (slot & 31);
+            if (!(f & 0x8000u) || (unsigned)tx >= (unsigned)kTileW || (unsigned)ty >= (unsigned)kTileH ||
+                slot >= N)
+                continue;
+            __hip_atomic_fetch_or(&sh.pend[(slot >> 3) * kBlock + ty * kTileW + tx],
+                                  1u << (8 * j + (slot & 7)), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
 }
 
-// LDS a tile needs: the intents halo and the pending bit-planes.
-template <int NMAX>
-struct PbasLds {
-    static constexpr int PW = (NMAX + 31) / 32;  // words per channel bit-plane
-    uint64_t halo[kHaloW * kHaloH];
-    uint32_t pend[4 * PW * kBlock];
-};
-
 // One updating frame on the 64x4 tile (bx, by); all 256 lanes of the block call it.
+//
+// The pixel's N sample words live in registers between one dense coalesced read
+// and one dense coalesced write of the sample planes: frame t-1's neighbour
+// writes and this frame's self-update are merged in registers with per-slot byte
+// masks, so no sample plane sees a partial-line write.  The Philox draws and the
+// 1/T tests do not depend on the classification, so the candidate self-update
+// slots are known first and their D-history bytes are fetched before the
+// samples, off the critical path.
+//
+// Classification runs two channels per 32-bit word (16-bit lanes: R|B and G|D).
+// The depth lane holds code - 1, so an empty depth slot (code 0) becomes 0xFFFF,
+// whose distance to any valid code is above every threshold and every d_min.
 template <int NMAX, bool NT>
 __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by, PbasLds<NMAX>& sh) {
-    constexpr int PW = PbasLds<NMAX>::PW;
-    uint64_t* lds = sh.halo;
-    uint32_t* pend = sh.pend;
-    const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
+    constexpr int NW = PbasLds<NMAX>::NW;
+    const int tid = threadIdx.x;
+    const int lx = tid % kTileW, ly = tid / kTileW;
     const int x0 = bx * kTileW, y0 = by * kTileH;
     const int x = x0 + lx, y = y0 + ly;
     const int W = a.W, H = a.H;
     const int64_t npix = a.npix;
     const int N = a.c.N;
 
-    const int tid = threadIdx.x;
     if (a.apply_pending) {
 #pragma unroll
-        for (int w = 0; w < 4 * PW; ++w) pend[w * kBlock + tid] = 0u;
-        stage_intents(lds, a.m.intents[(a.t - 1u) & 1u], x0, y0, H, W);
+        for (int w = 0; w < NW; ++w) sh.pend[w * kBlock + tid] = 0u;
+        __syncthreads();
+        scatter_intents<NMAX>(sh, a.m.intents[(a.t - 1u) & 1u], x0, y0, H, W, N);
         __syncthreads();
     }
     if (x >= W || y >= H) return;
@@ -155,12 +183,9 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
     const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
     const bool valid = dmm > 0u;
-    int I[4];
-    I[0] = px[0];
-    I[1] = px[1];
-    I[2] = px[2];
-    I[3] = (int)depth_code(dmm, a.c.depth_max_mm);
-    const uint32_t Iw = (uint32_t)I[0] | ((uint32_t)I[1] << 8) | ((uint32_t)I[2] << 16) | ((uint32_t)I[3] << 24);
+    const uint32_t I0 = px[0], I1 = px[1], I2 = px[2];
+    const uint32_t I3 = depth_code(dmm, a.c.depth_max_mm);
+    const uint32_t Iw = I0 | (I1 << 8) | (I2 << 16) | (I3 << 24);
 
     const float4 Rv = a.m.R[p];
     const float4 Tv = a.m.T[p];
@@ -171,9 +196,8 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     int S[4] = {(int)(Sv.x & 0xFFFFu), (int)(Sv.x >> 16), (int)(Sv.y & 0xFFFFu), (int)(Sv.y >> 16)};
     const bool active[4] = {true, true, true, valid};
 
-    // Two Philox blocks: 0 drives the self-update, 1 the neighbour update.
+    // Block 0 of the Philox draws drives the self-update.
     const U32x4 w0 = philox4x32_10((uint32_t)p, a.t, 0u, 0u, a.c.key0, a.c.key1);
-    const U32x4 w1 = philox4x32_10((uint32_t)p, a.t, 1u, 0u, a.c.key0, a.c.key1);
     const float inv16 = 1.0f / 65536.0f;
 
     // Self-update candidates: the 1/T test with T from before this frame.
@@ -195,49 +219,49 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     for (int k = 0; k < NMAX; ++k) sm[k] = k < N ? ld_sample<NT>(sp + (int64_t)k * npix) : 0u;
 
     // Frame t-1's neighbour writes into this pixel, before it is classified: slot k
-    // of channel j takes this pixel's previous value where bit k of plane j is set.
+    // of channel j takes this pixel's previous value where its bit is set.
     if (a.apply_pending) {
-        gather_pending<PW>(lds, pend, lx, ly, tid, lastw, N);
-        uint32_t pw[4][PW];
+        const uint32_t keep = (lastw >> 24) != 0u ? 0xFFFFFFFFu : 0x00FFFFFFu;  // depth at t-1?
+        uint32_t pw[NW];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int w = 0; w < PW; ++w) pw[j][w] = pend[(j * PW + w) * kBlock + tid];
+        for (int w = 0; w < NW; ++w) pw[w] = sh.pend[w * kBlock + tid] & keep;
 #pragma unroll
         for (int k = 0; k < NMAX; ++k) {
-            const int w = k >> 5, b = k & 31;
-            // all-ones where the bit is set, then one byte lane per channel
-            const uint32_t m0 = (uint32_t)((int32_t)(pw[0][w] << (31 - b)) >> 31);
-            const uint32_t m1 = (uint32_t)((int32_t)(pw[1][w] << (31 - b)) >> 31);
-            const uint32_t m2 = (uint32_t)((int32_t)(pw[2][w] << (31 - b)) >> 31);
-            const uint32_t m3 = (uint32_t)((int32_t)(pw[3][w] << (31 - b)) >> 31);
-            const uint32_t bm = (m0 & 0x000000FFu) | (m1 & 0x0000FF00u) | (m2 & 0x00FF0000u) | (m3 & 0xFF000000u);
+            const uint32_t bm = slot_byte_mask(pw[k >> 3], k);
             sm[k] = (sm[k] & ~bm) | (lastw & bm);
         }
     }
 
-    // Classification: an integer distance d is within R iff d <= ceil(R) - 1.
-    int thr[4];
+    // Classification: an integer distance d is within R iff d < min(ceil(R), 256)
+    // (no d is within a threshold R <= 0 or NaN).
+    uint32_t lim[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) thr[j] = (int)fminf(ceilf(R[j]), 256.0f) - 1;
-    int cnt[4] = {0, 0, 0, 0};
-    int dmn[4] = {255, 255, 255, 255};
+    for (int j = 0; j < 4; ++j) lim[j] = R[j] > 0.0f ? (uint32_t)fminf(ceilf(R[j]), 256.0f) : 0u;
+    const u16x2 I_rb = h2(I0 | (I2 << 16));
+    const u16x2 I_gd = h2(I1 | (((I3 - 1u) & 0xFFFFu) << 16));
+    const u16x2 L_rb = h2(lim[0] | (lim[2] << 16));
+    const u16x2 L_gd = h2(lim[1] | (lim[3] << 16));
+    const u16x2 cap = {0x200, 0x200};
+    const u16x2 one5 = {15, 15};
+    u16x2 cnt_rb = {0, 0}, cnt_gd = {0, 0};
+    u16x2 dmn_rb = {255, 255}, dmn_gd = {255, 255};
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         if (k < N) {
             const uint32_t s = sm[k];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int dd = abs((int)((s >> (8 * j)) & 0xFFu) - I[j]);
-                cnt[j] += dd <= thr[j] ? 1 : 0;
-                dmn[j] = min(dmn[j], dd);
-            }
-            const int b3 = (int)(s >> 24);
-            const int dd = b3 != 0 ? abs(b3 - I[3]) : 256;  // empty depth slot: never within R
-            cnt[3] += dd <= thr[3] ? 1 : 0;
-            dmn[3] = min(dmn[3], dd);
+            const u16x2 s_rb = h2(s & 0x00FF00FFu);
+            const u16x2 s_gd = h2(((s >> 8) & 0x00FF00FFu) - 0x00010000u);
+            const u16x2 d_rb = __builtin_elementwise_max(s_rb, I_rb) - __builtin_elementwise_min(s_rb, I_rb);
+            const u16x2 d_gd = __builtin_elementwise_max(s_gd, I_gd) - __builtin_elementwise_min(s_gd, I_gd);
+            dmn_rb = __builtin_elementwise_min(dmn_rb, d_rb);
+            dmn_gd = __builtin_elementwise_min(dmn_gd, d_gd);
+            // (min(d, 512) - lim) is negative, bit 15 set, iff d < lim
+            cnt_rb = cnt_rb + ((d_rb - L_rb) >> one5);
+            cnt_gd = cnt_gd + ((__builtin_elementwise_min(d_gd, cap) - L_gd) >> one5);
         }
     }
+    const int cnt[4] = {cnt_rb.x, cnt_gd.x, cnt_rb.y, cnt_gd.y};
+    const int dmn[4] = {dmn_rb.x, dmn_gd.x, dmn_rb.y, dmn_gd.y};
     bool F[4], upd[4];
     bool fg = false;
 #pragma unroll
@@ -248,14 +272,23 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     }
     a.m.mask[p] = fg ? (uint8_t)255 : (uint8_t)0;
 
-    // Self-update: sample slot ks[j] takes I_j, its D slot takes d_min.
+    // Self-update: sample slot ks[j] takes I_j (byte masks from bit-words built
+    // in registers), its D slot takes d_min.
+    {
+        uint32_t sw[NW];
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) {
-        uint32_t v = sm[k];
+        for (int w = 0; w < NW; ++w) {
+            uint32_t v = 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (upd[j] && ks[j] == k) v = (v & ~(0xFFu << (8 * j))) | ((uint32_t)I[j] << (8 * j));
-        sm[k] = v;
+            for (int j = 0; j < 4; ++j)
+                v |= (upd[j] && (ks[j] >> 3) == w) ? 1u << (8 * j + (ks[j] & 7)) : 0u;
+            sw[w] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            const uint32_t bm = slot_byte_mask(sw[k >> 3], k);
+            sm[k] = (sm[k] & ~bm) | (Iw & bm);
+        }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
@@ -264,7 +297,9 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             *byte_at(a.m.dhist, npix, ks[j], p, j) = (uint8_t)dmn[j];
         }
 
-    // Neighbour update with probability 1/T (T from before this frame): record the intent.
+    // Neighbour update with probability 1/T (T from before this frame): record the
+    // intent; block 1 of the draws drives it.
+    const U32x4 w1 = philox4x32_10((uint32_t)p, a.t, 1u, 0u, a.c.key0, a.c.key1);
     uint64_t intent = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {

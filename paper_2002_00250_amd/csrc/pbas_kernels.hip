@@ -78,14 +78,23 @@ void launch_step_nt(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
     else hipLaunchKernelGGL((pbas_step_kernel<NMAX, false>), grid, dim3(kBlock), 0, s, a);
 }
 
-// Register capacity for the N sample words: the smallest instantiated NMAX >= N.
+// Register capacity for the N sample words: the smallest instantiated NMAX >= N
+// (multiples of 4 up to 40, then 48, 56, 64).
 void launch_step_n(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
-    const int n = a.c.N;
-    if (n <= 8) launch_step_nt<8>(a, grid, s);
-    else if (n <= 16) launch_step_nt<16>(a, grid, s);
-    else if (n <= 24) launch_step_nt<24>(a, grid, s);
-    else if (n <= 40) launch_step_nt<40>(a, grid, s);
-    else launch_step_nt<64>(a, grid, s);
+    switch ((a.c.N + 3) / 4) {
+        case 0: case 1: case 2: launch_step_nt<8>(a, grid, s); break;
+        case 3: launch_step_nt<12>(a, grid, s); break;
+        case 4: launch_step_nt<16>(a, grid, s); break;
+        case 5: launch_step_nt<20>(a, grid, s); break;
+        case 6: launch_step_nt<24>(a, grid, s); break;
+        case 7: launch_step_nt<28>(a, grid, s); break;
+        case 8: launch_step_nt<32>(a, grid, s); break;
+        case 9: launch_step_nt<36>(a, grid, s); break;
+        case 10: launch_step_nt<40>(a, grid, s); break;
+        case 11: case 12: launch_step_nt<48>(a, grid, s); break;
+        case 13: case 14: launch_step_nt<56>(a, grid, s); break;
+        default: launch_step_nt<64>(a, grid, s); break;
+    }
 }
 
 }  // namespace
