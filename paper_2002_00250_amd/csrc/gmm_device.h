@@ -141,6 +141,12 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
         key[k] = m.w[k] / sqrtf(m.v[k]);
         idx[k] = k;
     }
+    // The network swaps nothing unless some adjacent pair is out of order, which in a
+    // static scene is rare: skip it when no lane of the wavefront needs a swap.
+    bool unsorted = false;
+#pragma unroll
+    for (int k = 1; k < K; ++k) unsorted = unsorted || key[k] > key[k - 1];
+    if (__any(unsorted))
 #pragma unroll
     for (int i = 1; i < K; ++i) {
 #pragma unroll

@@ -43,16 +43,25 @@ __device__ __forceinline__ uint8_t* byte_at(uint32_t* plane0, int64_t npix, int 
 }
 
 // Sample planes are touched once per frame: non-temporal when the device's
-// resident model state exceeds the last-level cache (see gmm_kernels.hip).
-template <bool NT>
-__device__ __forceinline__ uint32_t ld_sample(const uint32_t* p) {
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
+// resident model state exceeds the last-level cache (see gmm_kernels.hip).  A slot
+// is read and written through a raw buffer resource over its plane (base uniform
+// across the wavefront, range = one plane, so the hardware drops any access
+// outside it) with the pixel's 32-bit byte offset: no per-slot address is held in
+// vector registers.
+constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const uint32_t* plane0, uint32_t plane_bytes,
+                                                            int k) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(plane0) + (size_t)k * (plane_bytes >> 2),
+                                             (short)0, (int)plane_bytes, kBufferWord3);
 }
 template <bool NT>
-__device__ __forceinline__ void st_sample(uint32_t* p, uint32_t v) {
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
+__device__ __forceinline__ uint32_t ld_slot(const uint32_t* plane0, uint32_t plane_bytes, int k, uint32_t boff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(plane0, plane_bytes, k), boff, 0, NT ? 2 : 0);
+}
+template <bool NT>
+__device__ __forceinline__ void st_slot(uint32_t* plane0, uint32_t plane_bytes, int k, uint32_t boff, uint32_t v) {
+    __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(plane0, plane_bytes, k), boff, 0, NT ? 2 : 0);
 }
 
 // Stage the intents of the tile and its 1-pixel halo into LDS.
@@ -146,6 +155,7 @@ __device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint64_
 }
 
 // One updating frame on the 64x4 tile (bx, by); all 256 lanes of the block call it.
+// N lies in [NLO, NMAX]: slots below NLO need no run-time bound check.
 //
 // The pixel's N sample words live in registers between one dense coalesced read
 // and one dense coalesced write of the sample planes: frame t-1's neighbour
@@ -158,8 +168,9 @@ __device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint64_
 // Classification runs two channels per 32-bit word (16-bit lanes: R|B and G|D).
 // The depth lane holds code - 1, so an empty depth slot (code 0) becomes 0xFFFF,
 // whose distance to any valid code is above every threshold and every d_min.
-template <int NMAX, bool NT>
+template <int NMAX, int NLO, bool NT>
 __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by, PbasLds<NMAX>& sh) {
+    static_assert(NLO >= 1 && NLO <= NMAX, "bad register capacity class");
     constexpr int NW = PbasLds<NMAX>::NW;
     const int tid = threadIdx.x;
     const int lx = tid % kTileW, ly = tid / kTileW;
@@ -214,23 +225,10 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     for (int j = 0; j < 4; ++j) dold[j] = cand[j] ? (int)*byte_at(a.m.dhist, npix, ks[j], p, j) : 0;
 
     uint32_t sm[NMAX];
-    const uint32_t* sp = a.m.samples + p;
+    const uint32_t boff = (uint32_t)p * 4u;
+    const uint32_t pbytes = (uint32_t)npix * 4u;  // npix <= 2^28
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) sm[k] = k < N ? ld_sample<NT>(sp + (int64_t)k * npix) : 0u;
-
-    // Frame t-1's neighbour writes into this pixel, before it is classified: slot k
-    // of channel j takes this pixel's previous value where its bit is set.
-    if (a.apply_pending) {
-        const uint32_t keep = (lastw >> 24) != 0u ? 0xFFFFFFFFu : 0x00FFFFFFu;  // depth at t-1?
-        uint32_t pw[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) pw[w] = sh.pend[w * kBlock + tid] & keep;
-#pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            const uint32_t bm = slot_byte_mask(pw[k >> 3], k);
-            sm[k] = (sm[k] & ~bm) | (lastw & bm);
-        }
-    }
+    for (int k = 0; k < NMAX; ++k) sm[k] = (k < NLO || k < N) ? ld_slot<NT>(a.m.samples, pbytes, k, boff) : 0u;
 
     // Classification: an integer distance d is within R iff d < min(ceil(R), 256)
     // (no d is within a threshold R <= 0 or NaN).
@@ -245,9 +243,22 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     const u16x2 one5 = {15, 15};
     u16x2 cnt_rb = {0, 0}, cnt_gd = {0, 0};
     u16x2 dmn_rb = {255, 255}, dmn_gd = {255, 255};
+
+    // Frame t-1's neighbour writes into this pixel come first: slot k of channel j
+    // takes this pixel's previous value where its bit is set.
+    uint32_t pw[NW];
+    const uint32_t keep = (lastw >> 24) != 0u ? 0xFFFFFFFFu : 0x00FFFFFFu;  // depth at t-1?
+#pragma unroll
+    for (int w = 0; w < NW; ++w) pw[w] = a.apply_pending ? sh.pend[w * kBlock + tid] & keep : 0u;
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
-        if (k < N) {
+        // Keep the per-slot work next to its sample: without the fence the scheduler
+        // runs the mask arithmetic of every slot ahead of the loads and holds N more
+        // registers.
+        if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+        const uint32_t bm = slot_byte_mask(pw[k >> 3], k);
+        sm[k] = (sm[k] & ~bm) | (lastw & bm);
+        if (k < NLO || k < N) {
             const uint32_t s = sm[k];
             const u16x2 s_rb = h2(s & 0x00FF00FFu);
             const u16x2 s_gd = h2(((s >> 8) & 0x00FF00FFu) - 0x00010000u);
@@ -260,6 +271,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             cnt_gd = cnt_gd + ((__builtin_elementwise_min(d_gd, cap) - L_gd) >> one5);
         }
     }
+    __builtin_amdgcn_sched_barrier(0);
     const int cnt[4] = {cnt_rb.x, cnt_gd.x, cnt_rb.y, cnt_gd.y};
     const int dmn[4] = {dmn_rb.x, dmn_gd.x, dmn_rb.y, dmn_gd.y};
     bool F[4], upd[4];
@@ -327,10 +339,14 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         T[j] = fminf(fmaxf(tt, a.c.T_lower), a.c.T_upper);
     }
 
-    uint32_t* so = a.m.samples + p;
+    // The store loop rebuilds each plane's descriptor (a few scalar instructions)
+    // rather than keeping N of them alive across the frame; the empty asm hides
+    // that the base is the one the loads used.
+    uint32_t* sbase = a.m.samples;
+    asm volatile("" : "+s"(sbase));
 #pragma unroll
     for (int k = 0; k < NMAX; ++k)
-        if (k < N) st_sample<NT>(so + (int64_t)k * npix, sm[k]);
+        if (k < NLO || k < N) st_slot<NT>(sbase, pbytes, k, boff, sm[k]);
     a.m.R[p] = make_float4(R[0], R[1], R[2], R[3]);
     a.m.T[p] = make_float4(T[0], T[1], T[2], T[3]);
     a.m.S[p] = make_uint2((uint32_t)S[0] | ((uint32_t)S[1] << 16), (uint32_t)S[2] | ((uint32_t)S[3] << 16));

@@ -18,10 +18,13 @@ __global__ __launch_bounds__(256) void pbas_fill_kernel(PbasStepArgs a) {
     if (p < a.npix) fill_pixel(a, p);
 }
 
+// Register capacity class NMAX serves N in [class_min(NMAX), NMAX].
+constexpr int class_min(int nmax) { return nmax <= 8 ? 2 : (nmax <= 40 ? nmax - 3 : nmax - 7); }
+
 template <int NMAX, bool NT>
 __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
     __shared__ PbasLds<NMAX> sh;
-    pbas_tile<NMAX, NT>(a, blockIdx.x, blockIdx.y, sh);
+    pbas_tile<NMAX, class_min(NMAX), NT>(a, blockIdx.x, blockIdx.y, sh);
 }
 
 // Apply the intents of the last processed frame (read-out of the logical state).
@@ -79,7 +82,7 @@ void launch_step_nt(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
 }
 
 // Register capacity for the N sample words: the smallest instantiated NMAX >= N
-// (multiples of 4 up to 40, then 48, 56, 64).
+// (multiples of 4 up to 40, then 48, 56, 64), so that N >= class_min(NMAX).
 void launch_step_n(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
     switch ((a.c.N + 3) / 4) {
         case 0: case 1: case 2: launch_step_nt<8>(a, grid, s); break;

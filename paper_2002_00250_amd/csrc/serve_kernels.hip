@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void serve_kernel(const ServeEntry* __restrict
             const int p = local * 256 + (int)threadIdx.x;
             if (p < e.p.npix) pbas::fill_pixel(e.p, p);
         } else {
-            pbas::pbas_tile<NP, NT>(e.p, local % e.tiles_x, local / e.tiles_x, sh);
+            pbas::pbas_tile<NP, 2, NT>(e.p, local % e.tiles_x, local / e.tiles_x, sh);  // any N <= NP
         }
         __syncthreads();  // the next tile reuses the LDS
     }
