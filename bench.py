@@ -294,6 +294,57 @@ def adjoint_main(args):
     print(json.dumps(out), flush=True)
 
 
+def eval_main(args):
+    """Evaluation counters on 1280x720: per-frame confusion counts of a GMM K=5 model's
+    mask against ground truth accumulated on the device, the Sec. 5 indicators from them,
+    and the counting kernel timed on its own (2 B/px: mask + ground truth)."""
+    import torch
+    from paper_2002_00250_amd import fgs
+    from synth import Scene, preset
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
+    sc = Scene(preset("hd_1280x720"))
+    frames = [sc.frame(t) for t in range(32)]
+    rgb = torch.from_numpy(np.stack([f[0] for f in frames])).to(dev)
+    dep = torch.from_numpy(np.stack([f[1] for f in frames]).view(np.int16)).to(dev)
+    gt = torch.from_numpy(np.stack([f[2] for f in frames])).to(dev)
+    gp = fgs.fgs_gmm_params_default()
+    gp.Kc, gp.Kd = KC, KD
+    m = fgs.Model(fgs.FGS_GMM, H, W, gp, stream=stream)
+    for t in range(len(frames)):
+        fgs.fgs_push_frame(m.handle, rgb[t].data_ptr(), 3 * W, dep[t].data_ptr(), 2 * W, fgs.FGS_MEM_DEVICE)
+        if t >= 8:
+            m.eval_accumulate(gt[t])
+    counts = m.eval_read(reset=True)
+    K = args.steps
+    for _ in range(20):
+        m.eval_accumulate(gt[-1])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(K):
+        m.eval_accumulate(gt[-1])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / K * 1e3
+    m.close()
+    ind = indicators_from(counts)
+    out = {"metric": "evaluation counters: confusion-count kernel time per 1280x720 frame", "value": round(us, 3),
+           "unit": "us", "higher_is_better": False, "n_gpus": 1, "steps": K,
+           "GBs": round(2 * H * W / (us * 1e-6) / 1e9, 1),
+           "counts_tp_tn_fp_fn": list(counts), "indicators": {k: round(v, 5) for k, v in ind.items()},
+           "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "GMM Kc=Kd=5 1280x720, frames 8..31 scored against ground truth"}}
+    print(json.dumps(out), flush=True)
+
+
+def indicators_from(c):
+    tp, tn, fp, fn = c
+    d = lambda a, b: a / b if b else float("nan")
+    return {"PWC": 100.0 * d(fn + fp, tp + tn + fp + fn), "FNR": d(fn, tp + fn), "FPR": d(fp, fp + tn),
+            "Si": d(tp, tp + fp + fn)}
+
+
 def table1_main(args):
     """The resolutions of the paper's performance table (RGB / depth: 480p/480p, 720p/480p,
     720p/720p, 1080p/720p; depth upscaled in the kernel when smaller), one stream at a time,
@@ -362,6 +413,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--adjoint", action="store_true", help="time the GMM adjoint window step instead")
     ap.add_argument("--table1", action="store_true", help="time the paper's Table 1 resolutions instead")
+    ap.add_argument("--eval", action="store_true", help="time the evaluation counters instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -384,6 +436,9 @@ def main():
         return
     if args.table1:
         table1_main(args)
+        return
+    if args.eval:
+        eval_main(args)
         return
 
     # A dedicated stream (the legacy null stream has handle 0, which the library reads as

@@ -190,6 +190,27 @@ fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem whe
 fgs_status fgs_mask_device_ptr(fgs_model* m, const uint8_t** out);
 
 /*
+ * Evaluation counters (Sec. 5).  The paper scores masks by PWC = 100 (FN + FP) /
+ * (TP + TN + FP + FN), FNR = FN / (TP + FN), FPR = FP / (FP + TN) and
+ * Si = TP / (TP + FP + FN), all functions of the confusion counts against a
+ * ground-truth mask (foreground = positive).
+ *
+ * fgs_eval_accumulate compares the model's current mask with `gt` (H x W bytes,
+ * nonzero = foreground, rows gt_stride >= W bytes apart, in host or device memory
+ * per `where`) and adds TP, TN, FP, FN to a device-resident accumulator owned by
+ * the model, on the model's stream, without waiting for the device.  A host gt is
+ * copied to pinned staging before the call returns (the caller may reuse it); a
+ * device gt is read in stream order.  The accumulator starts at zero.
+ * INVALID_ARG for a NULL gt, a short stride or a bad `where`; BAD_STATE before the
+ * first push (no mask yet).
+ */
+fgs_status fgs_eval_accumulate(fgs_model* m, const uint8_t* gt, int64_t gt_stride, fgs_mem where);
+
+/* Wait for the model's stream and write the accumulated counts to counts[0..3] =
+ * TP, TN, FP, FN (host memory).  reset != 0 then clears the accumulator. */
+fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset);
+
+/*
  * Model state, serialised in a fixed layout (little-endian):
  *   header (64 bytes): uint32 magic 0x53534746 ("FGSS"), uint32 version (1),
  *     uint32 algo, int32 H, int32 W, int32 A, int32 B, int32 reserved,

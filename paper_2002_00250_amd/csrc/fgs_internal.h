@@ -135,6 +135,15 @@ int serve_pbas_nmax(int N);  // register capacity class of a PBAS model
 hipError_t serve_launch(const ServeEntry* entries, const int32_t* prefix, int n, int total_tiles,
                         int gmm_K, int pbas_nmax, bool streaming, hipStream_t s);
 
+// ---------------------------------------------------------- evaluation ----
+// Device counters of the evaluation: kEvalSlots partial sums per count, count c
+// (TP, TN, FP, FN) at acc[c * kEvalSlots ...]; the reader adds the slots.
+constexpr int kEvalSlots = 64;
+// acc += TP, TN, FP, FN of mask (rows W bytes apart) against gt.
+hipError_t eval_launch_count(const uint8_t* mask, const uint8_t* gt, int64_t gt_stride, int H, int W,
+                             unsigned long long* acc, hipStream_t s);
+hipError_t eval_launch_zero(unsigned long long* acc, hipStream_t s);
+
 // -------------------------------------------------------- diagnostics ----
 hipError_t diag_launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                               hipStream_t s);

@@ -27,6 +27,12 @@ struct fgs_model {
     uint8_t* dev_in;
     hipEvent_t stage_done;
     bool stage_busy;
+    // evaluation (allocated on the first fgs_eval_accumulate)
+    unsigned long long* eval_acc;  // device: TP, TN, FP, FN, kEvalSlots partial sums each
+    uint8_t* gt_stage;             // pinned host copy of a host ground truth
+    uint8_t* gt_dev;               // its device copy
+    hipEvent_t gt_done;
+    bool gt_busy;
     int64_t t;          // frames pushed
     bool pending;       // PBAS: intents of frame t-1 not yet applied
     bool poisoned;

@@ -388,6 +388,12 @@ fgs_status fgs_destroy(fgs_model* m) {
     (void)hipStreamSynchronize(m->stream);
     if (m->dev) (void)hipFree(m->dev);
     if (m->dev_in) (void)hipFree(m->dev_in);
+    if (m->eval_acc) (void)hipFree(m->eval_acc);
+    if (m->gt_dev) (void)hipFree(m->gt_dev);
+    if (m->gt_stage) {
+        (void)hipEventDestroy(m->gt_done);
+        (void)hipHostFree(m->gt_stage);
+    }
     if (m->host_stage) {
         (void)hipEventDestroy(m->stage_done);
         (void)hipHostFree(m->host_stage);
@@ -481,6 +487,86 @@ fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem whe
 fgs_status fgs_mask_device_ptr(fgs_model* m, const uint8_t** out) {
     if (!m || !out) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
     *out = m->mask;
+    return FGS_OK;
+}
+
+namespace {
+
+fgs_status ensure_eval(fgs_model* m) {
+    if (m->eval_acc) return FGS_OK;
+    hipError_t e = hipMalloc((void**)&m->eval_acc, 4 * kEvalSlots * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        m->eval_acc = nullptr;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "evaluation counters: %s", hipGetErrorString(e));
+    }
+    FGS_HIP(m, eval_launch_zero(m->eval_acc, m->stream));
+    return FGS_OK;
+}
+
+fgs_status ensure_gt_staging(fgs_model* m) {
+    if (m->gt_stage) return FGS_OK;
+    hipError_t e = hipHostMalloc((void**)&m->gt_stage, (size_t)m->npix, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        m->gt_stage = nullptr;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "pinned ground-truth staging: %s", hipGetErrorString(e));
+    }
+    e = hipMalloc((void**)&m->gt_dev, (size_t)m->npix);
+    if (e != hipSuccess) {
+        (void)hipHostFree(m->gt_stage);
+        m->gt_stage = nullptr;
+        m->gt_dev = nullptr;
+        return fail(FGS_ERR_OUT_OF_MEMORY, "device ground-truth staging: %s", hipGetErrorString(e));
+    }
+    FGS_HIP(m, hipEventCreateWithFlags(&m->gt_done, hipEventDisableTiming));
+    m->gt_busy = false;
+    return FGS_OK;
+}
+
+}  // namespace
+
+fgs_status fgs_eval_accumulate(fgs_model* m, const uint8_t* gt, int64_t gt_stride, fgs_mem where) {
+    if (!m || !gt) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    if (gt_stride < m->W) return fail(FGS_ERR_INVALID_ARG, "ground-truth stride %lld < W", (long long)gt_stride);
+    if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
+        return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    if (m->t == 0) return fail(FGS_ERR_BAD_STATE, "no frame has been pushed");
+    fgs_status st = ensure_eval(m);
+    if (st != FGS_OK) return st;
+    const uint8_t* dgt = gt;
+    int64_t gs = gt_stride;
+    if (where == FGS_MEM_HOST) {
+        st = ensure_gt_staging(m);
+        if (st != FGS_OK) return st;
+        if (m->gt_busy) FGS_HIP(m, hipEventSynchronize(m->gt_done));
+        for (int y = 0; y < m->H; ++y)
+            std::memcpy(m->gt_stage + (size_t)y * m->W, gt + (size_t)y * gt_stride, (size_t)m->W);
+        FGS_HIP(m, hipMemcpyAsync(m->gt_dev, m->gt_stage, (size_t)m->npix, hipMemcpyHostToDevice, m->stream));
+        FGS_HIP(m, hipEventRecord(m->gt_done, m->stream));
+        m->gt_busy = true;
+        dgt = m->gt_dev;
+        gs = m->W;
+    }
+    FGS_HIP(m, eval_launch_count(m->mask, dgt, gs, m->H, m->W, m->eval_acc, m->stream));
+    return FGS_OK;
+}
+
+fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset) {
+    if (!m || !counts) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    if (!m->eval_acc) {
+        for (int i = 0; i < 4; ++i) counts[i] = 0;
+        return FGS_OK;
+    }
+    unsigned long long v[4 * kEvalSlots];
+    FGS_HIP(m, hipMemcpyAsync(v, m->eval_acc, sizeof v, hipMemcpyDeviceToHost, m->stream));
+    FGS_HIP(m, hipStreamSynchronize(m->stream));
+    for (int i = 0; i < 4; ++i) {
+        uint64_t c = 0;
+        for (int k = 0; k < kEvalSlots; ++k) c += (uint64_t)v[i * kEvalSlots + k];
+        counts[i] = c;
+    }
+    if (reset) FGS_HIP(m, eval_launch_zero(m->eval_acc, m->stream));
     return FGS_OK;
 }
 

@@ -87,6 +87,8 @@ def _load():
         "fgs_push_frame_scaled": (S, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32, c_int32]),
         "fgs_get_mask": (S, [c_void_p, c_void_p, c_int64, c_int32]),
         "fgs_mask_device_ptr": (S, [c_void_p, POINTER(c_void_p)]),
+        "fgs_eval_accumulate": (S, [c_void_p, c_void_p, c_int64, c_int32]),
+        "fgs_eval_read": (S, [c_void_p, POINTER(c_uint64), c_int32]),
         "fgs_state_size": (S, [c_void_p, POINTER(c_size_t)]),
         "fgs_copy_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
         "fgs_set_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
@@ -186,6 +188,17 @@ def fgs_mask_device_ptr(m: int) -> int:
     out = c_void_p()
     _check(_load().fgs_mask_device_ptr(c_void_p(m), byref(out)))
     return out.value
+
+
+def fgs_eval_accumulate(m: int, gt: int, gt_stride: int, where: int) -> None:
+    _check(_load().fgs_eval_accumulate(c_void_p(m), c_void_p(gt), gt_stride, where))
+
+
+def fgs_eval_read(m: int, reset: bool = False) -> tuple:
+    """(TP, TN, FP, FN) accumulated so far."""
+    out = (c_uint64 * 4)()
+    _check(_load().fgs_eval_read(c_void_p(m), out, 1 if reset else 0))
+    return tuple(int(v) for v in out)
 
 
 def fgs_state_size(m: int) -> int:
@@ -419,6 +432,19 @@ class Model:
         out = np.empty((self.H, self.W), np.uint8)
         fgs_get_mask(self.handle, out.ctypes.data, self.W, FGS_MEM_HOST)
         return out
+
+    def eval_accumulate(self, gt) -> None:
+        """Add the confusion counts of the current mask against gt (uint8 [H, W], nonzero =
+        foreground; numpy array or cuda tensor) to the model's device counters."""
+        if isinstance(gt, np.ndarray):
+            g = np.ascontiguousarray(gt, np.uint8)
+            fgs_eval_accumulate(self.handle, g.ctypes.data, g.strides[0], FGS_MEM_HOST)
+        else:
+            fgs_eval_accumulate(self.handle, gt.data_ptr(), gt.stride(0), FGS_MEM_DEVICE)
+
+    def eval_read(self, reset: bool = False) -> tuple:
+        """(TP, TN, FP, FN) accumulated since creation or the last reset."""
+        return fgs_eval_read(self.handle, reset)
 
     def mask_into(self, out) -> None:
         """Device-to-device copy of the latest mask into a uint8 [H, W] cuda tensor."""

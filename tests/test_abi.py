@@ -71,6 +71,14 @@ def test_errors_without_device(libfgs):
         fgs.fgs_create(fgs.FGS_PBAS, 10, 10, p)
     assert "N = 65" in str(e.value)
     assert fgs.fgs_status_str(4) == "bad state"
+    # NULL handles are refused before any device work
+    for call in (lambda: fgs.fgs_eval_accumulate(0, 0, 16, fgs.FGS_MEM_HOST),
+                 lambda: fgs.fgs_eval_read(0),
+                 lambda: fgs.fgs_push_frame(0, 0, 0, 0, 0, fgs.FGS_MEM_HOST),
+                 lambda: fgs.fgs_get_mask(0, 0, 16, fgs.FGS_MEM_HOST)):
+        with pytest.raises(fgs.FgsError) as e:
+            call()
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG
 
 
 def test_state_pack_unpack_roundtrip():
