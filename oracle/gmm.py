@@ -30,8 +30,13 @@ What the paper fixes (Sec. 3.1) and what is read in
   With no valid depth (or w_d = 0) this is exactly the Stauffer-Grimson test
   "the pixel matches none of the background Gaussians".
 
+Update rate of the matched mean and variance (R-06 and its variant): rho = alpha
+(``rho_mode`` 0), or rho = alpha / w_k* with w_k* the matched weight after its
+update and before renormalisation (``rho_mode`` 1; the rule of OpenCV's mixture
+model, which Sec. 3.1 names as a basis of the authors' GMM).
+
 Per-pixel step (both models; X is the model's input vector, C its channel
-count, a = 1 - alpha, rho = alpha, lam2 = lambda*lambda):
+count, a = 1 - alpha, rho as above, lam2 = lambda*lambda):
 
   distances  e = X - mu_k;  d2_k = ((e0*e0) + e1*e1) + e2*e2  (C = 3) or e0*e0;
              q_k = d2_k / v_k
@@ -79,6 +84,7 @@ class GmmParams:
     v_min_d: float = 1.0      # 1 depth code (about 4 cm, Sec. 4.2)
     w_depth: float = 1.0
     depth_max_mm: int = DEPTH_MAX_MM
+    rho_mode: int = 0          # 0: rho = alpha; 1: rho = alpha / w (matched, updated)
 
 
 @dataclass
@@ -142,12 +148,11 @@ def first_match(w: np.ndarray, q: np.ndarray, lam2) -> np.ndarray:
 
 
 def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarray,
-                   alpha, lam2, w_init, v_init, v_min) -> Mixture:
+                   alpha, lam2, w_init, v_init, v_min, rho_over_w: bool = False) -> Mixture:
     """Stauffer-Grimson update + replacement + renormalisation + ranking where ``active``."""
     f = mix.w.dtype.type
     K, C = mix.mu.shape[0], mix.mu.shape[1]
     a = f(1) - alpha
-    rho = alpha
     ks = first_match(mix.w, q, lam2)
     matched = ks >= 0
     w = mix.w.copy()
@@ -156,6 +161,8 @@ def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarra
     for k in range(K):
         hit = matched & (ks == k)
         w[k] = np.where(hit, a * mix.w[k] + alpha, a * mix.w[k])
+        # rho is used only where hit (there w >= alpha > 0)
+        rho = alpha / np.where(hit, w[k], f(1)) if rho_over_w else alpha
         mu_new = np.empty_like(mix.mu[k])
         for c in range(C):
             mu_new[c] = mix.mu[k, c] + rho * (X[c] - mix.mu[k, c])
@@ -236,10 +243,11 @@ class GmmRef:
         self.last_has_term = has_term
 
         ones = np.ones((self.H, self.W), np.bool_)
+        rw = self.p.rho_mode == 1
         self.colour = update_mixture(self.colour, Xc, qc, ones, c["alpha"], lam2, c["w_init"],
-                                     c["v_init_c"], c["v_min_c"])
+                                     c["v_init_c"], c["v_min_c"], rw)
         self.depth = update_mixture(self.depth, Xd, qd, valid, c["alpha"], lam2, c["w_init"],
-                                    c["v_init_d"], c["v_min_d"])
+                                    c["v_init_d"], c["v_min_d"], rw)
         self.t += 1
         return mask
 

@@ -348,3 +348,52 @@ def test_vectorised_equals_scalar_brute_force():
         s = g.state_planes()
         for k in out:
             np.testing.assert_array_equal(s[k], out[k], err_msg=f"{k} frame {t}")
+
+
+@pytest.mark.parametrize("rho_mode", [1, 0])
+def test_rho_over_w_makes_mean_the_weighted_sample_mean(rho_mode):
+    # With rho = alpha / w (w the matched weight after its update) and weights that sum
+    # to 1, w*mu of every Gaussian obeys m_t = (1 - alpha) m_{t-1} + alpha X_t [matched],
+    # like w_t = (1 - alpha) w_{t-1} + alpha [matched]; so mu_t = m_t / w_t is the
+    # exponentially weighted mean of the samples the Gaussian was matched with.  Two far
+    # clusters, samples within +-2 of their centre (always matched by their own Gaussian),
+    # fp64.  With rho = alpha the identity must fail.
+    alpha = 0.05
+    p = _params(Kc=2, Kd=1, alpha=alpha, rho_mode=rho_mode)
+    n, T = 6, 80
+    A = np.array([50.0, 60.0, 70.0])
+    B = np.array([200.0, 190.0, 180.0])
+    g = GmmRef(1, n, p, dtype=np.float64)
+    st = dict(g.state_planes())
+    st["w_c"] = np.array([[[0.75] * n], [[0.25] * n]])
+    mu = np.zeros((2, 3, 1, n))
+    mu[0, :, 0, :] = A[:, None]
+    mu[1, :, 0, :] = B[:, None]
+    st["mu_c"] = mu
+    st["v_c"] = np.full((2, 1, n), 400.0)
+    g.set_state_planes(st)
+    rng = np.random.default_rng(3)
+    wA, wB = np.full(n, 0.75), np.full(n, 0.25)
+    mA, mB = wA[:, None] * A, wB[:, None] * B
+    worst = 0.0
+    for t in range(T):
+        pickA = rng.random(n) < 0.6
+        X = np.where(pickA[:, None], A, B) + rng.integers(-2, 3, size=(n, 3))
+        g.step(X.astype(np.uint8).reshape(1, n, 3), np.zeros((1, n), np.uint16))
+        wA = (1 - alpha) * wA + alpha * pickA
+        wB = (1 - alpha) * wB + alpha * ~pickA
+        mA = (1 - alpha) * mA + alpha * X * pickA[:, None]
+        mB = (1 - alpha) * mB + alpha * X * ~pickA[:, None]
+        s = g.state_planes()
+        muc = s["mu_c"][:, :, 0, :]                     # [K, 3, n]
+        slotA = np.argmin(np.abs(muc[:, 0, :] - A[0]), axis=0)
+        for i in range(n):
+            a_, b_ = slotA[i], 1 - slotA[i]
+            np.testing.assert_allclose(s["w_c"][a_, 0, i], wA[i], rtol=1e-12)
+            np.testing.assert_allclose(s["w_c"][b_, 0, i], wB[i], rtol=1e-12)
+            worst = max(worst, np.abs(muc[a_, :, i] - mA[i] / wA[i]).max(),
+                        np.abs(muc[b_, :, i] - mB[i] / wB[i]).max())
+    if rho_mode == 1:
+        assert worst < 1e-9
+    else:
+        assert worst > 0.05
