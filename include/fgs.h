@@ -68,7 +68,7 @@ typedef struct fgs_model fgs_model; /* opaque, owned by the library */
  * foreground iff Z = (delta_c - lambda^2) + w_depth*(delta_d - lambda^2) >= 0,
  * the depth term present only where depth > 0.  Update (Stauffer-Grimson):
  * first Gaussian with q < lambda^2 matches, w <- (1-alpha)w (+alpha if matched),
- * matched mean/variance move with rate alpha, v >= v_min; no match replaces the
+ * matched mean/variance move with rate rho (rho_mode), v >= v_min; no match replaces the
  * last Gaussian by (w_init, X, v_init); weights renormalised; ranked by
  * w/sqrt(v), stable, descending.  The depth model is updated only where
  * depth > 0.  Supported (Kc,Kd): (k,k) for k = 1..7, and (7,3).
@@ -76,7 +76,7 @@ typedef struct fgs_model fgs_model; /* opaque, owned by the library */
 typedef struct fgs_gmm_params {
     uint32_t struct_size; /* = sizeof(fgs_gmm_params) */
     int32_t Kc, Kd;
-    float alpha;          /* learning rate (also the mean/variance rate) */
+    float alpha;          /* learning rate (weights; the mean/variance rate is rho_mode's) */
     float lambda;         /* match threshold in standard deviations */
     float T_bg;           /* background weight fraction */
     float w_init;         /* weight of a replacement Gaussian */
@@ -84,6 +84,11 @@ typedef struct fgs_gmm_params {
     float v_init_d, v_min_d; /* depth variance: new Gaussian, floor */
     float w_depth;        /* weight of the depth term in Z */
     int32_t depth_max_mm; /* depth full scale: code = floor((255*D + M/2)/M), >= 1 */
+    int32_t rho_mode;     /* rate of the matched mean and variance: 0 rho = alpha;
+                             1 rho = alpha / w, w the matched weight after its update and
+                             before renormalisation (OpenCV's mixture rule, which Sec. 3.1
+                             names as a basis).  Appended field: a caller passing the
+                             earlier 52-byte struct (struct_size 52) gets rho = alpha. */
 } fgs_gmm_params;
 
 /*
@@ -124,8 +129,8 @@ const char* fgs_last_error(void);
 
 /* Fill *p with the default constants (the readings of Sec. 3.1 used by this
  * library: Kc = Kd = 3, alpha 0.01, lambda 2.5, T_bg 0.7, w_init 0.05,
- * v_init_c 675, v_min_c 12, v_init_d 25, v_min_d 1, w_depth 1, 10 m full scale).
- * INVALID_ARG if p is NULL. */
+ * v_init_c 675, v_min_c 12, v_init_d 25, v_min_d 1, w_depth 1, 10 m full scale,
+ * rho_mode 0).  INVALID_ARG if p is NULL. */
 fgs_status fgs_gmm_params_default(fgs_gmm_params* p);
 
 /* Fill *p with the default PBAS constants (Sec. 3.2: N = 20; the rest from the
@@ -278,7 +283,8 @@ fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy);
  * theta float[3]; rgb uint8[T][H][W][3]; depth uint16[T][H][W]; Z float[T][H][W];
  * has_term uint8[T][H][W]; dZ float[T][H][W]; dtheta double[3].  The caller
  * keeps the frames unchanged between forward and backward.  `hip_stream` as in
- * fgs_create.  Errors: INVALID_ARG, UNSUPPORTED (K), OUT_OF_MEMORY, BAD_STATE
+ * fgs_create.  Errors: INVALID_ARG, UNSUPPORTED (K, or rho_mode != 0: the adjoint
+ * is derived for rho = alpha), OUT_OF_MEMORY, BAD_STATE
  * (backward or records before forward), DEVICE.
  */
 typedef struct fgs_gmm_window fgs_gmm_window;

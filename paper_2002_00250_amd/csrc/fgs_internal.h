@@ -23,6 +23,7 @@ bool gmm_supported(int Kc, int Kd);
 struct GmmConsts {
     float alpha, lam, T_bg, w_init, v_init_c, v_min_c, v_init_d, v_min_d, w_depth;
     uint32_t depth_max_mm;
+    int32_t rho_over_w;  // 1: matched-Gaussian rate alpha / w
 };
 
 struct GmmStepArgs {

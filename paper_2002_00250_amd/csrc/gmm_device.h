@@ -35,7 +35,7 @@ template <int K, int C, bool REC>
 __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
                                              float alpha, float lam2, float T_bg, float w_init,
                                              float v_init, float v_min, bool& used,
-                                             float& delta, MixRec* rec) {
+                                             float& delta, MixRec* rec, bool rho_over_w = false) {
     float q[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -101,9 +101,12 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k != ks) continue;
+            // rate of the matched mean and variance: alpha, or alpha over the
+            // matched weight just updated (>= alpha > 0)
+            const float rho = rho_over_w ? alpha / m.w[k] : alpha;
             float mn[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) mn[c] = m.mu[k][c] + alpha * (X[c] - m.mu[k][c]);
+            for (int c = 0; c < C; ++c) mn[c] = m.mu[k][c] + rho * (X[c] - m.mu[k][c]);
             float e = X[0] - mn[0];
             float d2 = e * e;
 #pragma unroll
@@ -111,7 +114,7 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
                 e = X[c] - mn[c];
                 d2 = d2 + e * e;
             }
-            float vn = m.v[k] + alpha * (d2 - m.v[k]);
+            float vn = m.v[k] + rho * (d2 - m.v[k]);
             if (REC) rec->clamp = vn < v_min;
             vn = fmaxf(vn, v_min);
 #pragma unroll
@@ -251,10 +254,11 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     const float lam2 = a.c.lam * a.c.lam;
     bool used_c, used_d;
     float dc, dd;
+    const bool rw = a.c.rho_over_w != 0;
     mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
-                        a.c.v_min_c, used_c, dc, nullptr);
+                               a.c.v_min_c, used_c, dc, nullptr, rw);
     mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
-                        a.c.v_min_d, used_d, dd, nullptr);
+                               a.c.v_min_d, used_d, dd, nullptr, rw);
 
     const bool term_c = used_c;
     const bool term_d = valid && used_d;

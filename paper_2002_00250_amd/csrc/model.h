@@ -43,6 +43,11 @@ namespace fgs {
 
 // Thread-local error text + status (fgs_last_error).
 fgs_status set_error(fgs_status s, const char* fmt, ...);
+// GMM parameters from a caller's struct (NULL: defaults), honouring struct_size: the
+// current layout, or the earlier one without rho_mode (which then defaults to 0).
+fgs_status load_gmm_params(const void* src, fgs_gmm_params* out);
+// Launch constants of checked GMM parameters.
+GmmConsts gmm_consts(const fgs_gmm_params& p);
 // Non-temporal state traffic for this model's next launch (cache policy).
 bool model_use_streaming(const fgs_model* m);
 // Launch arguments of the model's next frame read from device frames; advances the

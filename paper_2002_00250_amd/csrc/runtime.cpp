@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -103,6 +104,7 @@ fgs_status check_gmm(const fgs_gmm_params& p) {
     if (p.struct_size != sizeof(fgs_gmm_params))
         return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u != %zu", p.struct_size,
                     sizeof(fgs_gmm_params));
+    if (p.rho_mode != 0 && p.rho_mode != 1) return fail(FGS_ERR_INVALID_ARG, "rho_mode %d not 0 or 1", p.rho_mode);
     if (!gmm_supported(p.Kc, p.Kd))
         return fail(FGS_ERR_INVALID_ARG, "unsupported (Kc, Kd) = (%d, %d)", p.Kc, p.Kd);
     if (!(p.alpha > 0.f && p.alpha < 1.f) || !(p.lambda > 0.f) || !(p.T_bg > 0.f && p.T_bg < 1.f) ||
@@ -150,6 +152,30 @@ fgs_status ensure_staging(fgs_model* m) {
 }
 
 }  // namespace
+
+fgs_status fgs::load_gmm_params(const void* src, fgs_gmm_params* p) {
+    fgs_gmm_params_default(p);
+    if (!src) return FGS_OK;
+    constexpr size_t kV1 = offsetof(fgs_gmm_params, rho_mode);  // layout before rho_mode
+    uint32_t size = 0;
+    std::memcpy(&size, src, sizeof size);
+    if (size == sizeof(fgs_gmm_params)) {
+        std::memcpy(p, src, sizeof *p);
+    } else if (size == kV1) {
+        std::memcpy(p, src, kV1);
+        p->struct_size = sizeof *p;
+    } else {
+        return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u is neither %zu nor %zu", size,
+                    sizeof(fgs_gmm_params), kV1);
+    }
+    return FGS_OK;
+}
+
+GmmConsts fgs::gmm_consts(const fgs_gmm_params& p) {
+    return GmmConsts{p.alpha,    p.lambda,   p.T_bg,    p.w_init,
+                     p.v_init_c, p.v_min_c,  p.v_init_d, p.v_min_d,
+                     p.w_depth,  (uint32_t)p.depth_max_mm, p.rho_mode == 1 ? 1 : 0};
+}
 
 bool fgs::model_use_streaming(const fgs_model* m) {
     if (m->cache_policy == FGS_CACHE_STREAM) return true;
@@ -282,8 +308,8 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
     fgs_pbas_params_default(&m->pp);
     fgs_status st = FGS_OK;
     if (algo == FGS_GMM) {
-        if (params) std::memcpy(&m->gp, params, sizeof m->gp);
-        st = check_gmm(m->gp);
+        st = load_gmm_params(params, &m->gp);
+        if (st == FGS_OK) st = check_gmm(m->gp);
     } else {
         if (params) std::memcpy(&m->pp, params, sizeof m->pp);
         st = check_pbas(m->pp);
@@ -292,9 +318,7 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         delete m;
         return st;
     }
-    m->gc = GmmConsts{m->gp.alpha, m->gp.lambda, m->gp.T_bg, m->gp.w_init, m->gp.v_init_c,
-                      m->gp.v_min_c, m->gp.v_init_d, m->gp.v_min_d, m->gp.w_depth,
-                      (uint32_t)m->gp.depth_max_mm};
+    m->gc = gmm_consts(m->gp);
     m->pc.N = m->pp.N;
     m->pc.min_matches = m->pp.min_matches;
     m->pc.R_incdec = m->pp.R_incdec;
@@ -724,10 +748,11 @@ fgs_status fgs_gmm_window_create(int32_t T, int32_t H, int32_t W, const fgs_gmm_
     if (!out) return fail(FGS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     fgs_gmm_params p;
-    fgs_gmm_params_default(&p);
-    if (params) std::memcpy(&p, params, sizeof p);
-    fgs_status st = check_gmm(p);
+    fgs_status st = load_gmm_params(params, &p);
+    if (st == FGS_OK) st = check_gmm(p);
     if (st != FGS_OK) return st;
+    if (p.rho_mode != 0)
+        return fail(FGS_ERR_UNSUPPORTED, "the adjoint is derived for rho = alpha (rho_mode 0)");
     if (p.Kc != p.Kd || !gmm_window_supported(p.Kc))
         return fail(FGS_ERR_UNSUPPORTED, "the adjoint supports Kc = Kd in 1..5, not (%d, %d)", p.Kc, p.Kd);
     if (T < 1 || H < 1 || W < 1 || (int64_t)H * W > kMaxPixels || checkpoint_every < 1)
@@ -741,8 +766,7 @@ fgs_status fgs_gmm_window_create(int32_t T, int32_t H, int32_t W, const fgs_gmm_
     w->K = p.Kc;
     w->E = checkpoint_every < T ? checkpoint_every : T;
     w->nseg = (T + w->E - 1) / w->E;
-    w->c = GmmConsts{p.alpha, p.lambda, p.T_bg, p.w_init, p.v_init_c, p.v_min_c, p.v_init_d,
-                     p.v_min_d, p.w_depth, (uint32_t)p.depth_max_mm};
+    w->c = gmm_consts(p);
     const size_t n = (size_t)w->npix, F = 6 * (size_t)w->K;
     const size_t o_rec = 0;
     const size_t o_ckpt = o_rec + align256((size_t)T * n * 8);

@@ -328,8 +328,8 @@ fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, c
     if (!s || !stream_id) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
     if (algo == FGS_GMM) {
         fgs_gmm_params p;
-        fgs_gmm_params_default(&p);
-        if (params) std::memcpy(&p, params, sizeof p);
+        const fgs_status ls = load_gmm_params(params, &p);
+        if (ls != FGS_OK) return ls;
         if (p.Kc != s->gmm_K || p.Kd != s->gmm_K)
             return fail(FGS_ERR_UNSUPPORTED, "this server runs GMM streams with Kc = Kd = %d", s->gmm_K);
     } else if (algo == FGS_PBAS) {

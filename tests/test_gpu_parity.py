@@ -33,6 +33,7 @@ def _gmm_params_c(p: GmmParams):
     c.alpha, c.lambda_, c.T_bg, c.w_init = p.alpha, p.lam, p.T_bg, p.w_init
     c.v_init_c, c.v_min_c, c.v_init_d, c.v_min_d = p.v_init_c, p.v_min_c, p.v_init_d, p.v_min_d
     c.w_depth, c.depth_max_mm = p.w_depth, p.depth_max_mm
+    c.rho_mode = p.rho_mode
     return c
 
 
@@ -130,6 +131,37 @@ def test_gmm_parity_edge_shapes(H, W, Kc, Kd, frames, mode):
                                              host_frames=mode == "host", strided=mode == "strided")
     log(f"gmm {H}x{W} K={Kc}/{Kd} {mode}: mask diff {diff}/{total}, state bad {bad}, not bit-equal {neq}")
     assert diff == 0 and bad == 0
+
+
+@pytest.mark.parametrize("Kc,Kd,alpha", [(3, 3, 0.01), (5, 5, 0.05), (7, 3, 0.001)])
+def test_gmm_parity_rho_over_w(Kc, Kd, alpha):
+    # update-rate variant rho = alpha / w: bit-exact like the default rate
+    cfg = preset("gmm_320x240", H=45, W=131, n_objects=3, illumination=True)
+    p = GmmParams(Kc=Kc, Kd=Kd, alpha=alpha, rho_mode=1)
+    diff, total, n, bad, neq = _run_gmm_pair(cfg, p, 40)
+    log(f"gmm rho=alpha/w K={Kc}/{Kd} alpha={alpha}: mask diff {diff}/{total}, state bad {bad}, "
+        f"not bit-equal {neq}")
+    assert diff == 0 and bad == 0 and neq == 0
+
+
+def test_gmm_legacy_params_struct_means_rho_alpha():
+    # a caller built against the 52-byte fgs_gmm_params (no rho_mode) gets rho = alpha,
+    # whatever follows the struct in memory
+    from paper_2002_00250_amd import fgs
+    cfg = preset("gmm_320x240", H=30, W=50, n_objects=2)
+    c = _gmm_params_c(GmmParams())
+    c.struct_size = 52
+    c.rho_mode = 1                        # beyond the declared size: must be ignored
+    sc = Scene(cfg)
+    ref = GmmRef(cfg.H, cfg.W, GmmParams())
+    m = fgs.Model(fgs.FGS_GMM, cfg.H, cfg.W, c)
+    for t in range(20):
+        rgb, D, _ = sc.frame(t)
+        m.push(rgb, D)
+        assert (m.mask_host() == ref.step(rgb, D)).all(), t
+    n, bad, neq = compare_gmm_state(m.state(), ref.state_planes())
+    m.close()
+    assert bad == 0 and neq == 0
 
 
 def test_gmm_parity_1280x720_k5_sampled_pixels():
