@@ -111,6 +111,12 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ u16x2 h2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
 __device__ __forceinline__ uint32_t w32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
+// Whether two float4 differ in any bit.
+__device__ __forceinline__ bool differs(float4 a, float4 b) {
+    return (__float_as_uint(a.x) ^ __float_as_uint(b.x)) | (__float_as_uint(a.y) ^ __float_as_uint(b.y)) |
+           (__float_as_uint(a.z) ^ __float_as_uint(b.z)) | (__float_as_uint(a.w) ^ __float_as_uint(b.w));
+}
+
 // Byte mask of the channels whose bit is set for slot k in bit-word `word`.
 __device__ __forceinline__ uint32_t slot_byte_mask(uint32_t word, int k) {
     const uint32_t bits = (word >> (k & 7)) & kLowBits;
@@ -302,11 +308,14 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             sm[k] = (sm[k] & ~bm) | (Iw & bm);
         }
     }
+    // A D-history byte is written only when it changes: on a static background d_min is
+    // mostly 0 or 1 and often equals the byte it replaces, and each write that is left
+    // out saves a partial-sector write to HBM.
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         if (upd[j]) {
             S[j] = S[j] - dold[j] + dmn[j];
-            *byte_at(a.m.dhist, npix, ks[j], p, j) = (uint8_t)dmn[j];
+            if (dold[j] != dmn[j]) *byte_at(a.m.dhist, npix, ks[j], p, j) = (uint8_t)dmn[j];
         }
 
     // Neighbour update with probability 1/T (T from before this frame): record the
@@ -347,9 +356,16 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 #pragma unroll
     for (int k = 0; k < NMAX; ++k)
         if (k < NLO || k < N) st_slot<NT>(sbase, pbytes, k, boff, sm[k]);
-    a.m.R[p] = make_float4(R[0], R[1], R[2], R[3]);
-    a.m.T[p] = make_float4(T[0], T[1], T[2], T[3]);
-    a.m.S[p] = make_uint2((uint32_t)S[0] | ((uint32_t)S[1] << 16), (uint32_t)S[2] | ((uint32_t)S[3] << 16));
+    // R, T and S are written only where they changed (bit for bit): on a static
+    // background R and T sit at their lower bounds and S moves only with D.
+    {
+        const float4 Rn = make_float4(R[0], R[1], R[2], R[3]);
+        const float4 Tn = make_float4(T[0], T[1], T[2], T[3]);
+        const uint2 Sn = make_uint2((uint32_t)S[0] | ((uint32_t)S[1] << 16), (uint32_t)S[2] | ((uint32_t)S[3] << 16));
+        if (differs(Rn, Rv)) a.m.R[p] = Rn;
+        if (differs(Tn, Tv)) a.m.T[p] = Tn;
+        if (Sn.x != Sv.x || Sn.y != Sv.y) a.m.S[p] = Sn;
+    }
     a.m.last[p] = Iw;
     a.m.intents[a.t & 1u][p] = intent;
 }
