@@ -98,12 +98,19 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
         m.w[k] = wk;
     }
     if (ks >= 0) {
+        // rate of the matched mean and variance: alpha, or alpha over the matched
+        // weight just updated (>= alpha > 0)
+        float rho = alpha;
+        if (rho_over_w) {
+            float wm = m.w[0];
+#pragma unroll
+            for (int k = 1; k < K; ++k)
+                if (k == ks) wm = m.w[k];
+            rho = alpha / wm;
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if (k != ks) continue;
-            // rate of the matched mean and variance: alpha, or alpha over the
-            // matched weight just updated (>= alpha > 0)
-            const float rho = rho_over_w ? alpha / m.w[k] : alpha;
             float mn[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) mn[c] = m.mu[k][c] + rho * (X[c] - m.mu[k][c]);
@@ -208,8 +215,10 @@ __device__ __forceinline__ void st_state(float4* p, float4 v) {
 }
 
 // One pixel of one frame: ingest, both mixtures' classify-and-update, the
-// combined decision, the mask, and the state write-back.
-template <int KC, int KD, bool NT>
+// combined decision, the mask, and the state write-back.  RW selects the rate of
+// the matched mean and variance: 0 alpha, 1 alpha / w, 2 as a.c.rho_over_w says
+// (a compile-time choice keeps the other path's registers out of the kernel).
+template <int KC, int KD, bool NT, int RW = 2>
 __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     constexpr int E = (KC + 3 * KD + 3) / 4;
     const int y = p / a.W;
@@ -254,7 +263,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     const float lam2 = a.c.lam * a.c.lam;
     bool used_c, used_d;
     float dc, dd;
-    const bool rw = a.c.rho_over_w != 0;
+    const bool rw = RW == 2 ? a.c.rho_over_w != 0 : RW == 1;
     mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
                                a.c.v_min_c, used_c, dc, nullptr, rw);
     mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,

@@ -26,10 +26,10 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <int KC, int KD, bool NT>
+template <int KC, int KD, bool NT, int RW>
 __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < a.npix) gmm_pixel<KC, KD, NT>(a, p);
+    if (p < a.npix) gmm_pixel<KC, KD, NT, RW>(a, p);
 }
 
 // Fresh model: w = 0, mu = 0, v = v_init (both mixtures).
@@ -96,13 +96,19 @@ __global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd
     }
 }
 
+template <int KC, int KD, int RW>
+void launch_step_rw(const GmmStepArgs& a, unsigned grid, hipStream_t s) {
+    if (a.streaming)
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, RW>), dim3(grid), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, RW>), dim3(grid), dim3(kBlock), 0, s, a);
+}
+
 template <int KC, int KD>
 hipError_t launch_step_t(const GmmStepArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)((a.npix + kBlock - 1) / kBlock);
-    if (a.streaming)
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (a.c.rho_over_w) launch_step_rw<KC, KD, 1>(a, grid, s);
+    else launch_step_rw<KC, KD, 0>(a, grid, s);
     return hipGetLastError();
 }
 
