@@ -74,8 +74,9 @@ hipError_t gmm_window_launch_backward(const GmmWindowArgs& a, int K, hipStream_t
 // --------------------------------------------------------------- PBAS ----
 // Device layout: samples[N] and dhist[N] uint32 planes (bytes R,G,B,depth), R and
 // T as one float4 per pixel, S as four uint16 per pixel (uint2), `last` = the
-// pixel's previous RGBD8 word, and two ping-pong planes of neighbour-update
-// intents (uint64 per pixel: 16 bits per channel = fire | dir<<12 | slot).
+// pixel's previous RGBD8 word, and two ping-pong planes of neighbour-update fire
+// bits (one byte per pixel, bit j: channel j wrote into a neighbour at that frame;
+// the neighbour and the slot follow from the pixel's Philox block 1 of that frame).
 struct PbasConsts {
     int32_t N, min_matches;
     float R_incdec, R_scale, T_inc, T_dec, T_lower, T_upper;
@@ -91,7 +92,7 @@ struct PbasPlanes {
     float4* T;
     uint2* S;
     uint32_t* last;
-    uint64_t* intents[2];
+    uint8_t* fire[2];
     uint8_t* mask;
 };
 
@@ -111,7 +112,7 @@ struct PbasStepArgs {
 hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConsts& c,
                                   hipStream_t s);
 hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s);
-hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, int N,
+hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, const PbasConsts& c,
                              hipStream_t s);
 hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out, hipStream_t s);
 hipError_t pbas_launch_import(const PbasPlanes& m, int npix, int N, const uint8_t* in,

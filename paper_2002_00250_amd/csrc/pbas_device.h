@@ -1,15 +1,15 @@
 // Per-tile device code of the RGB-D PBAS step (Sec. 3.2), shared by the per-frame
 // kernels and the multi-stream serving kernel.
 //
-// Neighbour updates without races or atomics.  At frame t a background pixel x
-// may write its 8-neighbour y's own value I(y,t) into a random sample of y.  All
-// such writes into y carry the same value and only y itself touches its D
+// Neighbour updates without races or atomics on HBM.  At frame t a background
+// pixel x may write its 8-neighbour y's own value I(y,t) into a random sample of
+// y.  All such writes into y carry the same value and only y itself touches its D
 // history, so their order does not matter; what matters is that y's
 // classification at frame t still sees the model of frame t-1.  Each pixel
-// therefore records its intent (fire, direction, slot per channel, 64 bits) at
-// frame t, and at frame t+1 every pixel first gathers the intents of its eight
-// neighbours from a 64x4 tile plus 1-pixel halo staged in LDS and applies the
-// writes aimed at it, using its stored previous value, before it classifies.
+// therefore records at frame t which channels fired (one byte), and at frame t+1
+// each tile recomputes the direction and slot of every write aimed into it from
+// the sources' Philox draws, collects them in LDS, and every pixel applies them,
+// using its stored previous value, before it classifies.
 //
 // Tile shape: a 256-lane workgroup covers 64 columns x 4 rows, one wavefront per
 // row, one pixel per lane, so each sample-plane access of a wavefront is 256
@@ -64,40 +64,11 @@ __device__ __forceinline__ void st_slot(uint32_t* plane0, uint32_t plane_bytes, 
     __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(plane0, plane_bytes, k), boff, 0, NT ? 2 : 0);
 }
 
-// Stage the intents of the tile and its 1-pixel halo into LDS.
-__device__ __forceinline__ void stage_intents(uint64_t* lds, const uint64_t* __restrict__ intents,
-                                              int x0, int y0, int H, int W) {
-    for (int i = threadIdx.x; i < kHaloW * kHaloH; i += kBlock) {
-        const int gx = x0 + (i % kHaloW) - 1;
-        const int gy = y0 + (i / kHaloW) - 1;
-        uint64_t v = 0;
-        if (gx >= 0 && gx < W && gy >= 0 && gy < H) v = intents[(int64_t)gy * W + gx];
-        lds[i] = v;
-    }
-}
-
-// Apply the neighbour writes aimed at pixel (lx,ly) of the tile: byte stores of
-// the pixel's previous value into the chosen sample slots.
-__device__ __forceinline__ void apply_pending(const uint64_t* lds, int lx, int ly, uint32_t lastw,
-                                              uint32_t* samples, int64_t npix, int p, int N) {
-#pragma unroll
-    for (int d = 0; d < 8; ++d) {
-        // the source x sits at offset delta[d] from this pixel and must have fired
-        // in the opposite direction 7 - d to reach it
-        const int ox = nb_dx(d), oy = nb_dy(d);
-        const uint64_t v = lds[(ly + 1 + oy) * kHaloW + (lx + 1 + ox)];
-        if (v == 0) continue;
-        const uint32_t want = 0x8u | (uint32_t)(7 - d);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t f = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
-            if ((f >> 12) != want) continue;
-            const uint32_t val = (lastw >> (8 * j)) & 0xFFu;
-            const int slot = (int)(f & 0x3Fu);
-            if ((j == 3 && val == 0u) || slot >= N) continue;  // y had no depth at that frame
-            *byte_at(samples, npix, slot, p, j) = (uint8_t)val;
-        }
-    }
+// Where channel j of pixel q sends its neighbour write at frame t: direction and
+// slot from the Philox block 1 word j of (q, t), as the pixel drew them then.
+__device__ __forceinline__ void intent_of(uint32_t word, int N, int& dir, int& slot) {
+    dir = (int)((word >> 13) & 7u);
+    slot = (int)(((word & 0x1FFFu) * (uint32_t)N) >> 13);  // < N
 }
 
 // Pending writes into a tile pixel are kept as slot bit-words: for sample slot k
@@ -131,28 +102,30 @@ struct PbasLds {
 };
 
 // Frame t-1's neighbour writes aimed at this tile, scattered from their sources:
-// every pixel of the tile and of its 1-pixel halo is read once, and each intent
-// that lands inside the tile sets its (slot, channel) bit in the destination's
-// bit-words with an LDS atomic OR.  Whether the destination had depth at t-1 is
-// checked by the destination.
+// every pixel of the tile and of its 1-pixel halo is read once (its fire byte); a
+// source that fired recomputes its Philox block 1 of frame t-1 for the direction
+// and slot, and each write that lands inside the tile sets its (slot, channel) bit
+// in the destination's bit-words with an LDS atomic OR.  Whether the destination
+// had depth at t-1 is checked by the destination.
 template <int NMAX>
-__device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint64_t* intents, int x0,
-                                                int y0, int H, int W, int N) {
+__device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint8_t* fire, int x0, int y0,
+                                                int H, int W, int N, uint32_t t_prev, uint32_t k0,
+                                                uint32_t k1) {
     for (int i = threadIdx.x; i < kHaloW * kHaloH; i += kBlock) {
         const int hx = i % kHaloW, hy = i / kHaloW;
         const int gx = x0 + hx - 1, gy = y0 + hy - 1;
         if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
-        const uint64_t v = intents[(int64_t)gy * W + gx];
-        if (v == 0) continue;
+        const int q = gy * W + gx;
+        const uint32_t fb = fire[q];
+        if (fb == 0u) continue;
+        const U32x4 w1 = philox4x32_10((uint32_t)q, t_prev, 1u, 0u, k0, k1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const uint32_t f = (uint32_t)(v >> (16 * j)) & 0xFFFFu;
-            const int d = (int)((f >> 12) & 7u);
+            if (!((fb >> j) & 1u)) continue;
+            int d, slot;
+            intent_of(w1.v[j], N, d, slot);
             const int tx = hx - 1 + nb_dx(d), ty = hy - 1 + nb_dy(d);
-            const int slot = (int)(f & 0x3Fu);
-            if (!(f & 0x8000u) || (unsigned)tx >= (unsigned)kTileW || (unsigned)ty >= (unsigned)kTileH ||
-                slot >= N)
-                continue;
+            if ((unsigned)tx >= (unsigned)kTileW || (unsigned)ty >= (unsigned)kTileH) continue;
             __hip_atomic_fetch_or(&sh.pend[(slot >> 3) * kBlock + ty * kTileW + tx],
                                   1u << (8 * j + (slot & 7)), __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -190,7 +163,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 #pragma unroll
         for (int w = 0; w < NW; ++w) sh.pend[w * kBlock + tid] = 0u;
         __syncthreads();
-        scatter_intents<NMAX>(sh, a.m.intents[(a.t - 1u) & 1u], x0, y0, H, W, N);
+        scatter_intents<NMAX>(sh, a.m.fire[(a.t - 1u) & 1u], x0, y0, H, W, N, a.t - 1u, a.c.key0, a.c.key1);
         __syncthreads();
     }
     if (x >= W || y >= H) return;
@@ -318,10 +291,11 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             if (dold[j] != dmn[j]) *byte_at(a.m.dhist, npix, ks[j], p, j) = (uint8_t)dmn[j];
         }
 
-    // Neighbour update with probability 1/T (T from before this frame): record the
-    // intent; block 1 of the draws drives it.
+    // Neighbour update with probability 1/T (T from before this frame): record that
+    // channel j fired; block 1 of the draws drives it, and the next frame's tiles
+    // recompute its direction and slot from the same block.
     const U32x4 w1 = philox4x32_10((uint32_t)p, a.t, 1u, 0u, a.c.key0, a.c.key1);
-    uint64_t intent = 0;
+    uint32_t fire = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         if (!active[j] || F[j]) continue;
@@ -329,10 +303,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         if ((float)(a1 >> 16) * inv16 * T[j] < 1.0f) {
             const int d = (int)((a1 >> 13) & 7u);
             const int nx = x + nb_dx(d), ny = y + nb_dy(d);
-            if (nx >= 0 && nx < W && ny >= 0 && ny < H) {
-                const uint32_t slot = ((a1 & 0x1FFFu) * (uint32_t)N) >> 13;
-                intent |= (uint64_t)(0x8000u | ((uint32_t)d << 12) | slot) << (16 * j);
-            }
+            if (nx >= 0 && nx < W && ny >= 0 && ny < H) fire |= 1u << j;
         }
     }
 
@@ -367,7 +338,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         if (Sn.x != Sv.x || Sn.y != Sv.y) a.m.S[p] = Sn;
     }
     a.m.last[p] = Iw;
-    a.m.intents[a.t & 1u][p] = intent;
+    a.m.fire[a.t & 1u][p] = (uint8_t)fire;
 }
 
 // Frames 0..N-1: sample slot t takes the frame; the mask is empty.

@@ -27,18 +27,35 @@ __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
     pbas_tile<NMAX, class_min(NMAX), NT>(a, blockIdx.x, blockIdx.y, sh);
 }
 
-// Apply the intents of the last processed frame (read-out of the logical state).
-__global__ __launch_bounds__(kBlock) void pbas_flush_kernel(PbasPlanes m, int H, int W,
-                                                            uint32_t t_prev, int N) {
-    __shared__ uint64_t lds[kHaloW * kHaloH];
-    const int lx = threadIdx.x % kTileW, ly = threadIdx.x / kTileW;
-    const int x0 = blockIdx.x * kTileW, y0 = blockIdx.y * kTileH;
-    stage_intents(lds, m.intents[t_prev & 1u], x0, y0, H, W);
-    __syncthreads();
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= W || y >= H) return;
-    const int p = y * W + x;
-    apply_pending(lds, lx, ly, m.last[p], m.samples, (int64_t)H * W, p, N);
+// Apply the neighbour writes of the last processed frame (read-out of the logical
+// state): each pixel looks at its 8 neighbours; a neighbour q in direction d that
+// fired recomputes its draws and counts if it aimed the opposite way, 7 - d (the
+// direction table is point symmetric).  Writes carry the pixel's own value of that
+// frame; the depth channel only where the pixel had depth.
+__global__ __launch_bounds__(256) void pbas_flush_kernel(PbasPlanes m, int H, int W, uint32_t t_prev,
+                                                         int N, uint32_t k0, uint32_t k1) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= H * W) return;
+    const int y = p / W, x = p - y * W;
+    const int64_t npix = (int64_t)H * W;
+    const uint32_t lastw = m.last[p];
+    const uint8_t* fire = m.fire[t_prev & 1u];
+    for (int d = 0; d < 8; ++d) {
+        const int qx = x + nb_dx(d), qy = y + nb_dy(d);
+        if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+        const int q = qy * W + qx;
+        const uint32_t fb = fire[q];
+        if (fb == 0u) continue;
+        const U32x4 w1 = philox4x32_10((uint32_t)q, t_prev, 1u, 0u, k0, k1);
+        for (int j = 0; j < 4; ++j) {
+            if (!((fb >> j) & 1u)) continue;
+            int dq, slot;
+            intent_of(w1.v[j], N, dq, slot);
+            const uint32_t val = (lastw >> (8 * j)) & 0xFFu;
+            if (dq != 7 - d || (j == 3 && val == 0u)) continue;
+            *byte_at(m.samples, npix, slot, p, j) = (uint8_t)val;
+        }
+    }
 }
 
 __global__ void pbas_init_state_kernel(PbasPlanes m, int npix, float4 Rl, float Tl) {
@@ -120,10 +137,10 @@ hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, int N,
+hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, const PbasConsts& c,
                              hipStream_t s) {
-    const dim3 grid((W + kTileW - 1) / kTileW, (H + kTileH - 1) / kTileH);
-    hipLaunchKernelGGL(pbas_flush_kernel, grid, dim3(kBlock), 0, s, m, H, W, t_prev, N);
+    hipLaunchKernelGGL(pbas_flush_kernel, dim3(blocks1d(H * W)), dim3(256), 0, s, m, H, W, t_prev, c.N,
+                       c.key0, c.key1);
     return hipGetLastError();
 }
 

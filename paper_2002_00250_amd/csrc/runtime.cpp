@@ -226,7 +226,7 @@ namespace {
 
 fgs_status flush_pending(fgs_model* m) {
     if (m->algo != FGS_PBAS || !m->pending) return FGS_OK;
-    FGS_HIP(m, pbas_launch_flush(m->pb, m->H, m->W, (uint32_t)(m->t - 1), m->pp.N, m->stream));
+    FGS_HIP(m, pbas_launch_flush(m->pb, m->H, m->W, (uint32_t)(m->t - 1), m->pc, m->stream));
     m->pending = false;
     return FGS_OK;
 }
@@ -364,8 +364,8 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         o_T = off;       off += align256(n * 16);
         o_S = off;       off += align256(n * 8);
         o_last = off;    off += align256(n * 4);
-        o_i0 = off;      off += align256(n * 8);
-        o_i1 = off;      off += align256(n * 8);
+        o_i0 = off;      off += align256(n);
+        o_i1 = off;      off += align256(n);
     }
     o_mask = off;
     off += align256(n);
@@ -387,8 +387,8 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         m->pb.T = reinterpret_cast<float4*>(m->dev + o_T);
         m->pb.S = reinterpret_cast<uint2*>(m->dev + o_S);
         m->pb.last = reinterpret_cast<uint32_t*>(m->dev + o_last);
-        m->pb.intents[0] = reinterpret_cast<uint64_t*>(m->dev + o_i0);
-        m->pb.intents[1] = reinterpret_cast<uint64_t*>(m->dev + o_i1);
+        m->pb.fire[0] = m->dev + o_i0;
+        m->pb.fire[1] = m->dev + o_i1;
         m->pb.mask = m->mask;
         e = hipMemsetAsync(m->dev, 0, off, m->stream);
         if (e == hipSuccess) e = pbas_launch_init_state(m->pb, m->npix, m->pc, m->stream);
