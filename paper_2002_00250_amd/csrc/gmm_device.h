@@ -31,11 +31,16 @@ struct MixRec {
 
 // Classify on the pre-update mixture (used, delta) and, if `active`, update it in
 // place.  With REC, also fill *rec.
+// With `chg`, also report which ranks may hold a different (mean, variance) than
+// before the step: bit r is set when the ranking moved another Gaussian to rank r
+// or when the Gaussian at rank r was matched or replaced (clear bits are certain).
 template <int K, int C, bool REC>
 __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
                                              float alpha, float lam2, float T_bg, float w_init,
                                              float v_init, float v_min, bool& used,
-                                             float& delta, MixRec* rec, bool rho_over_w = false) {
+                                             float& delta, MixRec* rec, bool rho_over_w = false,
+                                             uint32_t* chg = nullptr) {
+    if (chg) *chg = 0u;
     float q[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -188,6 +193,13 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
         for (int k = 0; k < K; ++k) pr |= (uint32_t)idx[k] << (3 * k);
         rec->perm = pr;
     }
+    if (chg) {
+        const int touched = ks >= 0 ? ks : K - 1;  // matched, or replaced
+        uint32_t c = 0;
+#pragma unroll
+        for (int r = 0; r < K; ++r) c |= (uint32_t)(idx[r] != r || idx[r] == touched) << r;
+        *chg = c;
+    }
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -214,13 +226,32 @@ __device__ __forceinline__ void st_state(float4* p, float4 v) {
     }
 }
 
+// Device layout of a GMM model (planes of npix float4, plane-major):
+//   core plane k (k < Kc):  (mu_r, mu_g, mu_b, v) of colour rank k;
+//   extra planes (E of them): the floats w_c[0..Kc-1], w_d[0..Kd-1], then
+//   (mu_d, v_d) of depth rank 0, 1, ..., packed four to a plane, zero padded.
+// Weights decay every frame, but a rank's mean and variance change only when its
+// Gaussian is matched, replaced or moved by the ranking, so the planes that hold
+// only means and variances can often be left unwritten.
+template <int KC, int KD>
+struct GmmLayout {
+    static constexpr int E = (KC + 3 * KD + 3) / 4;  // extra planes
+    static constexpr int w_c(int k) { return k; }
+    static constexpr int w_d(int k) { return KC + k; }
+    static constexpr int mu_d(int k) { return KC + KD + 2 * k; }
+    static constexpr int v_d(int k) { return KC + KD + 2 * k + 1; }
+};
+
 // One pixel of one frame: ingest, both mixtures' classify-and-update, the
 // combined decision, the mask, and the state write-back.  RW selects the rate of
 // the matched mean and variance: 0 alpha, 1 alpha / w, 2 as a.c.rho_over_w says
 // (a compile-time choice keeps the other path's registers out of the kernel).
+// A plane is stored only when some lane of the wavefront may have changed it
+// (the skip is wavefront-uniform, so every store still covers whole lines).
 template <int KC, int KD, bool NT, int RW = 2>
 __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
-    constexpr int E = (KC + 3 * KD + 3) / 4;
+    using L = GmmLayout<KC, KD>;
+    constexpr int E = L::E;
     const int y = p / a.W;
     const int x = p - y * a.W;
 
@@ -247,27 +278,34 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     Mix<KD, 1> md;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        mc.w[k] = core[k].x;
-        mc.mu[k][0] = core[k].y;
-        mc.mu[k][1] = core[k].z;
-        mc.mu[k][2] = core[k].w;
-        mc.v[k] = ex[k];
+        mc.w[k] = ex[L::w_c(k)];
+        mc.mu[k][0] = core[k].x;
+        mc.mu[k][1] = core[k].y;
+        mc.mu[k][2] = core[k].z;
+        mc.v[k] = core[k].w;
     }
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
-        md.w[k] = ex[KC + k];
-        md.mu[k][0] = ex[KC + KD + k];
-        md.v[k] = ex[KC + 2 * KD + k];
+        md.w[k] = ex[L::w_d(k)];
+        md.mu[k][0] = ex[L::mu_d(k)];
+        md.v[k] = ex[L::v_d(k)];
     }
 
     const float lam2 = a.c.lam * a.c.lam;
     bool used_c, used_d;
     float dc, dd;
+    uint32_t chg_c, chg_d;
     const bool rw = RW == 2 ? a.c.rho_over_w != 0 : RW == 1;
+    float4* so = a.state;
     mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
-                               a.c.v_min_c, used_c, dc, nullptr, rw);
+                               a.c.v_min_c, used_c, dc, nullptr, rw, &chg_c);
+    // the colour means and variances are final: store them before the depth step
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (__any((chg_c >> k) & 1u))
+            st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.mu[k][0], mc.mu[k][1], mc.mu[k][2], mc.v[k]));
     mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
-                               a.c.v_min_d, used_d, dd, nullptr, rw);
+                               a.c.v_min_d, used_d, dd, nullptr, rw, &chg_d);
 
     const bool term_c = used_c;
     const bool term_d = valid && used_d;
@@ -276,22 +314,30 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     const float Z = term_c ? (term_d ? tc + td : tc) : td;
     a.mask[p] = ((term_c || term_d) && Z >= 0.0f) ? (uint8_t)255 : (uint8_t)0;
 
-    float4* so = a.state;
+    // Which extra floats may change: the colour weights always (the colour mixture
+    // is updated every frame), the depth weights where depth > 0 (the depth mixture
+    // is updated only there), a depth mean and variance as the depth mixture reports.
 #pragma unroll
-    for (int k = 0; k < KC; ++k)
-        st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.w[k], mc.mu[k][0], mc.mu[k][1], mc.mu[k][2]));
-#pragma unroll
-    for (int k = 0; k < KC; ++k) ex[k] = mc.v[k];
+    for (int k = 0; k < KC; ++k) ex[L::w_c(k)] = mc.w[k];
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
-        ex[KC + k] = md.w[k];
-        ex[KC + KD + k] = md.mu[k][0];
-        ex[KC + 2 * KD + k] = md.v[k];
+        ex[L::w_d(k)] = md.w[k];
+        ex[L::mu_d(k)] = md.mu[k][0];
+        ex[L::v_d(k)] = md.v[k];
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,
-                  make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]));
+    for (int e = 0; e < E; ++e) {
+        bool ch = false;
+#pragma unroll
+        for (int i = 4 * e; i < 4 * e + 4; ++i) {
+            if (i < KC) ch = true;
+            else if (i < KC + KD) ch = ch || valid;
+            else if (i < KC + 3 * KD) ch = ch || ((chg_d >> ((i - KC - KD) >> 1)) & 1u);
+        }
+        if (__any(ch))
+            st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,
+                         make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]));
+    }
 }
 
 }  // namespace fgs

@@ -32,29 +32,34 @@ __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     if (p < a.npix) gmm_pixel<KC, KD, NT, RW>(a, p);
 }
 
+// Index of a float among the extra planes (the layout of gmm_device.h, for run-time
+// Kc, Kd): w_c[k], w_d[k], then (mu_d, v_d) pairs by rank.
+__device__ __forceinline__ int x_wc(int, int, int k) { return k; }
+__device__ __forceinline__ int x_wd(int Kc, int, int k) { return Kc + k; }
+__device__ __forceinline__ int x_mud(int Kc, int Kd, int k) { return Kc + Kd + 2 * k; }
+__device__ __forceinline__ int x_vd(int Kc, int Kd, int k) { return Kc + Kd + 2 * k + 1; }
+
+__device__ __forceinline__ float* f4(float4* s, int64_t i) { return reinterpret_cast<float*>(s + i); }
+__device__ __forceinline__ const float* f4(const float4* s, int64_t i) {
+    return reinterpret_cast<const float*>(s + i);
+}
+__device__ __forceinline__ float* xf(float4* s, int Kc, int64_t n, int64_t p, int idx) {
+    return f4(s, (int64_t)(Kc + idx / 4) * n + p) + idx % 4;
+}
+__device__ __forceinline__ float xg(const float4* s, int Kc, int64_t n, int64_t p, int idx) {
+    return f4(s, (int64_t)(Kc + idx / 4) * n + p)[idx % 4];
+}
+
 // Fresh model: w = 0, mu = 0, v = v_init (both mixtures).
 __global__ void gmm_init_kernel(float4* state, int Kc, int Kd, int npix, float v_init_c,
                                 float v_init_d) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= npix) return;
+    const int64_t n = npix;
     const int E = (Kc + 3 * Kd + 3) / 4;
-    for (int k = 0; k < Kc; ++k) state[(int64_t)k * npix + p] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int e = 0; e < E; ++e) {
-        float f[4];
-        for (int i = 0; i < 4; ++i) {
-            const int idx = 4 * e + i;
-            float val = 0.f;
-            if (idx < Kc) val = v_init_c;
-            else if (idx >= Kc + 2 * Kd && idx < Kc + 3 * Kd) val = v_init_d;
-            f[i] = val;
-        }
-        state[(int64_t)(Kc + e) * npix + p] = make_float4(f[0], f[1], f[2], f[3]);
-    }
-}
-
-__device__ __forceinline__ float* f4(float4* s, int64_t i) { return reinterpret_cast<float*>(s + i); }
-__device__ __forceinline__ const float* f4(const float4* s, int64_t i) {
-    return reinterpret_cast<const float*>(s + i);
+    for (int k = 0; k < Kc; ++k) state[(int64_t)k * n + p] = make_float4(0.f, 0.f, 0.f, v_init_c);
+    for (int e = 0; e < E; ++e) state[(int64_t)(Kc + e) * n + p] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = 0; k < Kd; ++k) *xf(state, Kc, n, p, x_vd(Kc, Kd, k)) = v_init_d;
 }
 
 // Canonical order: w_c[Kc], mu_c[Kc][3], v_c[Kc], w_d[Kd], mu_d[Kd], v_d[Kd], planes of npix.
@@ -64,15 +69,14 @@ __global__ void gmm_export_kernel(const float4* state, float* out, int Kc, int K
     const int64_t n = npix;
     for (int k = 0; k < Kc; ++k) {
         const float* c = f4(state, (int64_t)k * n + p);
-        out[(int64_t)k * n + p] = c[0];
-        for (int ch = 0; ch < 3; ++ch) out[(int64_t)(Kc + 3 * k + ch) * n + p] = c[1 + ch];
+        out[(int64_t)k * n + p] = xg(state, Kc, n, p, x_wc(Kc, Kd, k));
+        for (int ch = 0; ch < 3; ++ch) out[(int64_t)(Kc + 3 * k + ch) * n + p] = c[ch];
+        out[(int64_t)(4 * Kc + k) * n + p] = c[3];
     }
-    auto extra = [&](int idx) { return f4(state, (int64_t)(Kc + idx / 4) * n + p)[idx % 4]; };
-    for (int k = 0; k < Kc; ++k) out[(int64_t)(4 * Kc + k) * n + p] = extra(k);
     for (int k = 0; k < Kd; ++k) {
-        out[(int64_t)(5 * Kc + k) * n + p] = extra(Kc + k);
-        out[(int64_t)(5 * Kc + Kd + k) * n + p] = extra(Kc + Kd + k);
-        out[(int64_t)(5 * Kc + 2 * Kd + k) * n + p] = extra(Kc + 2 * Kd + k);
+        out[(int64_t)(5 * Kc + k) * n + p] = xg(state, Kc, n, p, x_wd(Kc, Kd, k));
+        out[(int64_t)(5 * Kc + Kd + k) * n + p] = xg(state, Kc, n, p, x_mud(Kc, Kd, k));
+        out[(int64_t)(5 * Kc + 2 * Kd + k) * n + p] = xg(state, Kc, n, p, x_vd(Kc, Kd, k));
     }
 }
 
@@ -80,19 +84,18 @@ __global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= npix) return;
     const int64_t n = npix;
+    const int E = (Kc + 3 * Kd + 3) / 4;
+    for (int e = 0; e < E; ++e) state[(int64_t)(Kc + e) * n + p] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int k = 0; k < Kc; ++k) {
         float* c = f4(state, (int64_t)k * n + p);
-        c[0] = in[(int64_t)k * n + p];
-        for (int ch = 0; ch < 3; ++ch) c[1 + ch] = in[(int64_t)(Kc + 3 * k + ch) * n + p];
+        for (int ch = 0; ch < 3; ++ch) c[ch] = in[(int64_t)(Kc + 3 * k + ch) * n + p];
+        c[3] = in[(int64_t)(4 * Kc + k) * n + p];
+        *xf(state, Kc, n, p, x_wc(Kc, Kd, k)) = in[(int64_t)k * n + p];
     }
-    const int E = (Kc + 3 * Kd + 3) / 4;
-    for (int idx = 0; idx < 4 * E; ++idx) {
-        float v = 0.f;
-        if (idx < Kc) v = in[(int64_t)(4 * Kc + idx) * n + p];
-        else if (idx < Kc + Kd) v = in[(int64_t)(5 * Kc + (idx - Kc)) * n + p];
-        else if (idx < Kc + 2 * Kd) v = in[(int64_t)(5 * Kc + Kd + (idx - Kc - Kd)) * n + p];
-        else if (idx < Kc + 3 * Kd) v = in[(int64_t)(5 * Kc + 2 * Kd + (idx - Kc - 2 * Kd)) * n + p];
-        f4(state, (int64_t)(Kc + idx / 4) * n + p)[idx % 4] = v;
+    for (int k = 0; k < Kd; ++k) {
+        *xf(state, Kc, n, p, x_wd(Kc, Kd, k)) = in[(int64_t)(5 * Kc + k) * n + p];
+        *xf(state, Kc, n, p, x_mud(Kc, Kd, k)) = in[(int64_t)(5 * Kc + Kd + k) * n + p];
+        *xf(state, Kc, n, p, x_vd(Kc, Kd, k)) = in[(int64_t)(5 * Kc + 2 * Kd + k) * n + p];
     }
 }
 
