@@ -10,7 +10,7 @@ namespace fgs {
 // rescale of millimetres to `full_scale_mm`, clamped to [1, 255].
 __device__ __forceinline__ uint32_t depth_code(uint32_t d_mm, uint32_t full_scale_mm) {
     if (d_mm == 0u) return 0u;
-    uint32_t q = (255u * d_mm + (full_scale_mm >> 1)) / full_scale_mm;
+    uint32_t q = (__umul24(255u, d_mm) + (full_scale_mm >> 1)) / full_scale_mm;  // d_mm < 2^16
     q = q < 1u ? 1u : q;
     return q > 255u ? 255u : q;
 }

@@ -68,7 +68,7 @@ __device__ __forceinline__ void st_slot(uint32_t* plane0, uint32_t plane_bytes, 
 // slot from the Philox block 1 word j of (q, t), as the pixel drew them then.
 __device__ __forceinline__ void intent_of(uint32_t word, int N, int& dir, int& slot) {
     dir = (int)((word >> 13) & 7u);
-    slot = (int)(((word & 0x1FFFu) * (uint32_t)N) >> 13);  // < N
+    slot = (int)(__umul24(word & 0x1FFFu, (uint32_t)N) >> 13);  // < N; 13 x 7 bits: 24-bit multiply
 }
 
 // Pending writes into a tile pixel are kept as slot bit-words: for sample slot k
@@ -197,7 +197,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     for (int j = 0; j < 4; ++j) {
         const uint32_t a0 = w0.v[j];
         cand[j] = active[j] && (float)(a0 >> 16) * inv16 * T[j] < 1.0f;
-        ks[j] = (int)(((a0 & 0xFFFFu) * (uint32_t)N) >> 16);
+        ks[j] = (int)(__umul24(a0 & 0xFFFFu, (uint32_t)N) >> 16);  // 16 x 7 bits: 24-bit multiply
     }
     int dold[4];
 #pragma unroll
@@ -315,7 +315,8 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         const float dbar = (float)S[j] / (float)N;
         const float r = (R[j] > dbar * a.c.R_scale) ? R[j] * rdn : R[j] * rup;
         R[j] = fmaxf(r, a.c.R_lower[j]);
-        const float tt = F[j] ? T[j] + a.c.T_inc / dbar : T[j] - a.c.T_dec / dbar;
+        const float q = (F[j] ? a.c.T_inc : a.c.T_dec) / dbar;  // one division, not two and a select
+        const float tt = F[j] ? T[j] + q : T[j] - q;
         T[j] = fminf(fmaxf(tt, a.c.T_lower), a.c.T_upper);
     }
 
