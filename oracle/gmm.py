@@ -30,6 +30,14 @@ What the paper fixes (Sec. 3.1) and what is read in
   With no valid depth (or w_d = 0) this is exactly the Stauffer-Grimson test
   "the pixel matches none of the background Gaussians".
 
+Decision variant (``decision`` 1; R-09 keeps the exponent terms only): each model's
+factor is Eq. (1) scaled by s for the background Gaussian that attains delta_m,
+P_m = s * exp(-delta_m / 2) / (2 pi v), v that Gaussian's variance (binary32 in
+the order exp, 2 pi * v, division, scaling); the product P = P_c * P_d where the
+depth term is present (else the single factor), and the pixel is foreground when
+P < tau.  Parity unpinned beyond its agreement with the log-sum rule when tau is
+set from equal variances (tests).
+
 Update rate of the matched mean and variance (R-06 and its variant): rho = alpha
 (``rho_mode`` 0), or rho = alpha / w_k* with w_k* the matched weight after its
 update and before renormalisation (``rho_mode`` 1; the rule of OpenCV's mixture
@@ -85,6 +93,9 @@ class GmmParams:
     w_depth: float = 1.0
     depth_max_mm: int = DEPTH_MAX_MM
     rho_mode: int = 0          # 0: rho = alpha; 1: rho = alpha / w (matched, updated)
+    decision: int = 0          # 0: Z = (d_c - lam^2) + w_d (d_d - lam^2) >= 0; 1: P < tau
+    density_scale: float = 10000.0   # s (Sec. 3.1 default)
+    density_threshold: float = 1.0   # tau
 
 
 @dataclass
@@ -133,10 +144,25 @@ def background_count(w: np.ndarray, T_bg) -> np.ndarray:
 
 def background_distance(q: np.ndarray, B: np.ndarray) -> np.ndarray:
     """delta = min over the B background Gaussians of q_k (defined where B >= 1)."""
+    return background_argmin(q, B)[0]
+
+
+def background_argmin(q: np.ndarray, B: np.ndarray):
+    """(delta, k): the minimum over the B background Gaussians and the first index attaining it."""
     delta = q[0].copy()
+    arg = np.zeros(q.shape[1:], np.int64)
     for k in range(1, q.shape[0]):
-        delta = np.where(k < B, np.minimum(delta, q[k]), delta)
-    return delta
+        better = (k < B) & (q[k] < delta)
+        delta = np.where(better, q[k], delta)
+        arg = np.where(better, k, arg)
+    return delta, arg
+
+
+def density_factor(delta: np.ndarray, v: np.ndarray, s) -> np.ndarray:
+    """s * exp(-delta/2) / (2 pi v): Eq. (1) scaled by s, for the Gaussian attaining delta."""
+    f = delta.dtype.type
+    e = np.exp(f(-0.5) * delta)
+    return f(s) * (e / (f(2.0 * np.pi) * v))
 
 
 def first_match(w: np.ndarray, q: np.ndarray, lam2) -> np.ndarray:
@@ -207,6 +233,7 @@ class GmmRef:
         self.depth = fresh_mixture(self.p.Kd, 1, H, W, f(self.p.v_init_d), self.dtype)
         self.t = 0
         self.last_Z = None
+        self.last_P = None
         self.last_has_term = None
 
     def constants(self):
@@ -230,15 +257,25 @@ class GmmRef:
         # Decision on the pre-update (ranked) models.
         used_c = self.colour.w[0] > 0
         used_d = self.depth.w[0] > 0
-        dc = background_distance(qc, background_count(self.colour.w, c["T_bg"]))
-        dd = background_distance(qd, background_count(self.depth.w, c["T_bg"]))
+        dc, kc = background_argmin(qc, background_count(self.colour.w, c["T_bg"]))
+        dd, kd = background_argmin(qd, background_count(self.depth.w, c["T_bg"]))
         term_c = used_c
         term_d = valid & used_d
         tc = dc - lam2
         td = c["w_depth"] * (dd - lam2)
         Z = np.where(term_c, np.where(term_d, tc + td, tc), td)
         has_term = term_c | term_d
-        mask = np.where(has_term & (Z >= 0), 255, 0).astype(np.uint8)
+        if self.p.decision == 1:
+            vc = np.take_along_axis(self.colour.v, kc[None], axis=0)[0]
+            vd = np.take_along_axis(self.depth.v, kd[None], axis=0)[0]
+            with np.errstate(over="ignore", under="ignore"):
+                Pc = density_factor(dc, vc, self.p.density_scale)
+                Pd = density_factor(dd, vd, self.p.density_scale)
+                P = np.where(term_c, np.where(term_d, Pc * Pd, Pc), Pd)
+            mask = np.where(has_term & (P < f(self.p.density_threshold)), 255, 0).astype(np.uint8)
+            self.last_P = np.where(has_term, P, f(0))
+        else:
+            mask = np.where(has_term & (Z >= 0), 255, 0).astype(np.uint8)
         self.last_Z = np.where(has_term, Z, f(0))
         self.last_has_term = has_term
 

@@ -397,3 +397,64 @@ def test_rho_over_w_makes_mean_the_weighted_sample_mean(rho_mode):
         assert worst < 1e-9
     else:
         assert worst > 0.05
+
+
+def _row_model(p, n, wc, muc, vc, wd, mud, vd, dtype=np.float32):
+    """A 1 x n model whose pixels all hold the same mixtures."""
+    g = GmmRef(1, n, p, dtype=dtype)
+    Kc, Kd = p.Kc, p.Kd
+    rep = lambda a, *shape: np.broadcast_to(np.array(a, dtype).reshape(*shape, 1, 1), shape + (1, n)).copy()
+    g.set_state_planes(dict(w_c=rep(wc, Kc), mu_c=rep(muc, Kc, 3), v_c=rep(vc, Kc),
+                            w_d=rep(wd, Kd), mu_d=rep(mud, Kd), v_d=rep(vd, Kd), t=5))
+    return g
+
+
+def test_density_decision_closed_form_at_the_mean():
+    # X on the mean of the only colour Gaussian, no depth: P = s / (2 pi v) (Eq. (1) at d = 0).
+    s_ = 10000.0
+    for v0 in (12.0, 27.5, 400.0, 675.0):
+        p = _params(Kc=3, Kd=1, decision=1, density_scale=s_)
+        X = [37, 140, 201]
+        g = _row_model(p, 1, [1, 0, 0], [X, [0, 0, 0], [0, 0, 0]], [v0, 675, 675], [0], [0], [25])
+        g.step(np.array(X, np.uint8).reshape(1, 1, 3), np.zeros((1, 1), np.uint16))
+        np.testing.assert_allclose(float(g.last_P[0, 0]), s_ / (2 * np.pi * v0), rtol=2e-6)
+
+
+@pytest.mark.parametrize("with_depth", [True, False])
+def test_density_decision_agrees_with_log_sum_rule(with_depth):
+    # One Gaussian per model, equal variances everywhere.  With tau = s^2 e^{-lam^2} /
+    # (4 pi^2 v_c v_d) (colour only: s e^{-lam^2/2} / (2 pi v_c)), "P < tau" is
+    # "delta_c + delta_d > 2 lam^2" (colour only: "delta_c > lam^2"): the log-sum rule
+    # (R-09, w_d = 1) must give the same masks except on the boundary itself.
+    rng = np.random.default_rng(7)
+    n, s_, lam = 4000, 10000.0, 2.5
+    Vc, Vd = 60.0, 4.0
+    mu_c, mu_code = np.array([120.0, 90.0, 60.0]), 100
+    tau = (s_ ** 2 * np.exp(-lam ** 2) / (4 * np.pi ** 2 * Vc * Vd)) if with_depth else \
+        (s_ * np.exp(-lam ** 2 / 2) / (2 * np.pi * Vc))
+    kw = dict(Kc=1, Kd=1, lam=lam, w_depth=1.0)
+    X = np.clip(mu_c + rng.normal(0, 14, size=(n, 3)), 0, 255).round().astype(np.uint8)
+    codes = np.clip(mu_code + rng.integers(-6, 7, size=n), 1, 255)
+    mm = np.round(codes * 10000 / 255).astype(np.uint16) if with_depth else np.zeros(n, np.uint16)
+    masks = []
+    for dec in (0, 1):
+        p = _params(decision=dec, density_scale=s_, density_threshold=float(tau), **kw)
+        g = _row_model(p, n, [1], [mu_c], [Vc], [1], [mu_code], [Vd], dtype=np.float64)
+        masks.append(g.step(X.reshape(1, n, 3), mm.reshape(1, n))[0])
+    dc = ((X - mu_c) ** 2).sum(1) / Vc
+    dd = (depth_q8(mm, 10000).astype(float) - mu_code) ** 2 / Vd if with_depth else 0.0
+    margin = np.abs(dc + dd - (2 if with_depth else 1) * lam ** 2)
+    differ = masks[0] != masks[1]
+    assert masks[0].any() and not masks[0].all()
+    assert not differ[margin > 1e-6].any()
+
+
+def test_density_decision_uses_the_gaussian_attaining_delta():
+    # Two background Gaussians (weights 0.5, 0.4 > T_bg together); X on the mean of the
+    # second: delta = 0 is attained by Gaussian 1, so P = s / (2 pi v_1), not v_0.
+    p = _params(Kc=3, Kd=1, decision=1, T_bg=0.7)
+    X = [200, 30, 90]
+    g = _row_model(p, 1, [0.5, 0.4, 0.1], [[10, 10, 10], X, [250, 0, 0]], [100.0, 33.0, 500.0],
+                   [0], [0], [25])
+    g.step(np.array(X, np.uint8).reshape(1, 1, 3), np.zeros((1, 1), np.uint16))
+    np.testing.assert_allclose(float(g.last_P[0, 0]), 10000.0 / (2 * np.pi * 33.0), rtol=2e-6)
