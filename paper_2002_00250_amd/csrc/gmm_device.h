@@ -34,12 +34,13 @@ struct MixRec {
 // With `chg`, also report which ranks may hold a different (mean, variance) than
 // before the step: bit r is set when the ranking moved another Gaussian to rank r
 // or when the Gaussian at rank r was matched or replaced (clear bits are certain).
+// With `vsel`, also the (pre-update) variance of the Gaussian attaining delta.
 template <int K, int C, bool REC>
 __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
                                              float alpha, float lam2, float T_bg, float w_init,
                                              float v_init, float v_min, bool& used,
                                              float& delta, MixRec* rec, bool rho_over_w = false,
-                                             uint32_t* chg = nullptr) {
+                                             uint32_t* chg = nullptr, float* vsel = nullptr) {
     if (chg) *chg = 0u;
     float q[K];
 #pragma unroll
@@ -78,6 +79,13 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
             delta = q[k];
             amin = k;
         }
+    if (vsel) {
+        float vs = m.v[0];
+#pragma unroll
+        for (int k = 1; k < K; ++k)
+            if (k == amin) vs = m.v[k];
+        *vsel = vs;
+    }
     if (REC) {
         rec->argmin = amin;
         rec->kstar = -1;
@@ -242,13 +250,20 @@ struct GmmLayout {
     static constexpr int v_d(int k) { return KC + KD + 2 * k + 1; }
 };
 
+// Scaled Eq. (1) factor of the Gaussian attaining delta (decision 1), in the order
+// the oracle rounds it: s * (exp(-delta/2) / (2 pi v)).
+__device__ __forceinline__ float density_factor(float delta, float v, float s) {
+    return s * (expf(-0.5f * delta) / (6.28318530717958647692f * v));
+}
+
 // One pixel of one frame: ingest, both mixtures' classify-and-update, the
 // combined decision, the mask, and the state write-back.  RW selects the rate of
-// the matched mean and variance: 0 alpha, 1 alpha / w, 2 as a.c.rho_over_w says
+// the matched mean and variance: 0 alpha, 1 alpha / w, 2 as a.c.rho_over_w says;
+// DEC the decision: 0 the Z rule, 1 the density product, 2 as a.c.decision says
 // (a compile-time choice keeps the other path's registers out of the kernel).
 // A plane is stored only when some lane of the wavefront may have changed it
 // (the skip is wavefront-uniform, so every store still covers whole lines).
-template <int KC, int KD, bool NT, int RW = 2>
+template <int KC, int KD, bool NT, int RW = 2, int DEC = 2>
 __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     using L = GmmLayout<KC, KD>;
     constexpr int E = L::E;
@@ -295,24 +310,35 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     bool used_c, used_d;
     float dc, dd;
     uint32_t chg_c, chg_d;
+    float vsel_c = 1.0f, vsel_d = 1.0f;
     const bool rw = RW == 2 ? a.c.rho_over_w != 0 : RW == 1;
+    const bool dec = DEC == 2 ? a.c.decision != 0 : DEC == 1;
     float4* so = a.state;
     mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
-                               a.c.v_min_c, used_c, dc, nullptr, rw, &chg_c);
+                               a.c.v_min_c, used_c, dc, nullptr, rw, &chg_c, DEC ? &vsel_c : nullptr);
     // the colour means and variances are final: store them before the depth step
 #pragma unroll
     for (int k = 0; k < KC; ++k)
         if (__any((chg_c >> k) & 1u))
             st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.mu[k][0], mc.mu[k][1], mc.mu[k][2], mc.v[k]));
     mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
-                               a.c.v_min_d, used_d, dd, nullptr, rw, &chg_d);
+                               a.c.v_min_d, used_d, dd, nullptr, rw, &chg_d, DEC ? &vsel_d : nullptr);
 
     const bool term_c = used_c;
     const bool term_d = valid && used_d;
-    const float tc = dc - lam2;
-    const float td = a.c.w_depth * (dd - lam2);
-    const float Z = term_c ? (term_d ? tc + td : tc) : td;
-    a.mask[p] = ((term_c || term_d) && Z >= 0.0f) ? (uint8_t)255 : (uint8_t)0;
+    bool fg;
+    if (DEC != 0 && dec) {
+        const float Pc = density_factor(dc, vsel_c, a.c.density_scale);
+        const float Pd = density_factor(dd, vsel_d, a.c.density_scale);
+        const float P = term_c ? (term_d ? Pc * Pd : Pc) : Pd;
+        fg = P < a.c.density_threshold;
+    } else {
+        const float tc = dc - lam2;
+        const float td = a.c.w_depth * (dd - lam2);
+        const float Z = term_c ? (term_d ? tc + td : tc) : td;
+        fg = Z >= 0.0f;
+    }
+    a.mask[p] = ((term_c || term_d) && fg) ? (uint8_t)255 : (uint8_t)0;
 
     // Which extra floats may change: the colour weights always (the colour mixture
     // is updated every frame), the depth weights where depth > 0 (the depth mixture

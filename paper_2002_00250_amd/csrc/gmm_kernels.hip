@@ -26,10 +26,12 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <int KC, int KD, bool NT, int RW>
+// GEN = false: the default rate and decision compiled in; GEN = true: both read
+// from the constants (any other choice).
+template <int KC, int KD, bool NT, bool GEN>
 __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < a.npix) gmm_pixel<KC, KD, NT, RW>(a, p);
+    if (p < a.npix) gmm_pixel<KC, KD, NT, GEN ? 2 : 0, GEN ? 2 : 0>(a, p);
 }
 
 // Index of a float among the extra planes (the layout of gmm_device.h, for run-time
@@ -99,19 +101,19 @@ __global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd
     }
 }
 
-template <int KC, int KD, int RW>
-void launch_step_rw(const GmmStepArgs& a, unsigned grid, hipStream_t s) {
+template <int KC, int KD, bool GEN>
+void launch_step_g(const GmmStepArgs& a, unsigned grid, hipStream_t s) {
     if (a.streaming)
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, RW>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, GEN>), dim3(grid), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, RW>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, GEN>), dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 template <int KC, int KD>
 hipError_t launch_step_t(const GmmStepArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)((a.npix + kBlock - 1) / kBlock);
-    if (a.c.rho_over_w) launch_step_rw<KC, KD, 1>(a, grid, s);
-    else launch_step_rw<KC, KD, 0>(a, grid, s);
+    if (a.c.rho_over_w || a.c.decision) launch_step_g<KC, KD, true>(a, grid, s);
+    else launch_step_g<KC, KD, false>(a, grid, s);
     return hipGetLastError();
 }
 

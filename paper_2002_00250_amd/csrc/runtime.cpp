@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cmath>
 #include <cstdarg>
 #include <cstddef>
 #include <cstdio>
@@ -105,6 +106,10 @@ fgs_status check_gmm(const fgs_gmm_params& p) {
         return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u != %zu", p.struct_size,
                     sizeof(fgs_gmm_params));
     if (p.rho_mode != 0 && p.rho_mode != 1) return fail(FGS_ERR_INVALID_ARG, "rho_mode %d not 0 or 1", p.rho_mode);
+    if (p.decision != 0 && p.decision != 1) return fail(FGS_ERR_INVALID_ARG, "decision %d not 0 or 1", p.decision);
+    if (!(p.density_scale > 0.f && p.density_scale < INFINITY) ||
+        !(p.density_threshold >= 0.f && p.density_threshold < INFINITY))
+        return fail(FGS_ERR_INVALID_ARG, "density_scale must be > 0 and density_threshold >= 0, both finite");
     if (!gmm_supported(p.Kc, p.Kd))
         return fail(FGS_ERR_INVALID_ARG, "unsupported (Kc, Kd) = (%d, %d)", p.Kc, p.Kd);
     if (!(p.alpha > 0.f && p.alpha < 1.f) || !(p.lambda > 0.f) || !(p.T_bg > 0.f && p.T_bg < 1.f) ||
@@ -156,25 +161,24 @@ fgs_status ensure_staging(fgs_model* m) {
 fgs_status fgs::load_gmm_params(const void* src, fgs_gmm_params* p) {
     fgs_gmm_params_default(p);
     if (!src) return FGS_OK;
-    constexpr size_t kV1 = offsetof(fgs_gmm_params, rho_mode);  // layout before rho_mode
+    // earlier layouts: up to depth_max_mm, then with rho_mode
+    constexpr size_t kV1 = offsetof(fgs_gmm_params, rho_mode);
+    constexpr size_t kV2 = offsetof(fgs_gmm_params, decision);
     uint32_t size = 0;
     std::memcpy(&size, src, sizeof size);
-    if (size == sizeof(fgs_gmm_params)) {
-        std::memcpy(p, src, sizeof *p);
-    } else if (size == kV1) {
-        std::memcpy(p, src, kV1);
-        p->struct_size = sizeof *p;
-    } else {
-        return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u is neither %zu nor %zu", size,
-                    sizeof(fgs_gmm_params), kV1);
-    }
+    if (size != sizeof(fgs_gmm_params) && size != kV1 && size != kV2)
+        return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u is none of %zu, %zu, %zu", size,
+                    sizeof(fgs_gmm_params), kV2, kV1);
+    std::memcpy(p, src, size);  // the fields it does not cover keep their defaults
+    p->struct_size = sizeof *p;
     return FGS_OK;
 }
 
 GmmConsts fgs::gmm_consts(const fgs_gmm_params& p) {
     return GmmConsts{p.alpha,    p.lambda,   p.T_bg,    p.w_init,
                      p.v_init_c, p.v_min_c,  p.v_init_d, p.v_min_d,
-                     p.w_depth,  (uint32_t)p.depth_max_mm, p.rho_mode == 1 ? 1 : 0};
+                     p.w_depth,  (uint32_t)p.depth_max_mm, p.rho_mode == 1 ? 1 : 0,
+                     p.decision == 1 ? 1 : 0, p.density_scale, p.density_threshold};
 }
 
 bool fgs::model_use_streaming(const fgs_model* m) {
@@ -268,6 +272,10 @@ fgs_status fgs_gmm_params_default(fgs_gmm_params* p) {
     p->v_min_d = 1.0f;
     p->w_depth = 1.0f;
     p->depth_max_mm = 10000;
+    p->rho_mode = 0;
+    p->decision = 0;
+    p->density_scale = 10000.0f;
+    p->density_threshold = 1.0f;
     return FGS_OK;
 }
 
@@ -751,8 +759,9 @@ fgs_status fgs_gmm_window_create(int32_t T, int32_t H, int32_t W, const fgs_gmm_
     fgs_status st = load_gmm_params(params, &p);
     if (st == FGS_OK) st = check_gmm(p);
     if (st != FGS_OK) return st;
-    if (p.rho_mode != 0)
-        return fail(FGS_ERR_UNSUPPORTED, "the adjoint is derived for rho = alpha (rho_mode 0)");
+    if (p.rho_mode != 0 || p.decision != 0)
+        return fail(FGS_ERR_UNSUPPORTED, "the adjoint is derived for rho = alpha and the Z score "
+                                         "(rho_mode 0, decision 0)");
     if (p.Kc != p.Kd || !gmm_window_supported(p.Kc))
         return fail(FGS_ERR_UNSUPPORTED, "the adjoint supports Kc = Kd in 1..5, not (%d, %d)", p.Kc, p.Kd);
     if (T < 1 || H < 1 || W < 1 || (int64_t)H * W > kMaxPixels || checkpoint_every < 1)

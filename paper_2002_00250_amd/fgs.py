@@ -44,7 +44,8 @@ class fgs_gmm_params(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("lambda_", ctypes.c_float), ("T_bg", ctypes.c_float),
                 ("w_init", ctypes.c_float), ("v_init_c", ctypes.c_float), ("v_min_c", ctypes.c_float),
                 ("v_init_d", ctypes.c_float), ("v_min_d", ctypes.c_float), ("w_depth", ctypes.c_float),
-                ("depth_max_mm", c_int32), ("rho_mode", c_int32)]
+                ("depth_max_mm", c_int32), ("rho_mode", c_int32), ("decision", c_int32),
+                ("density_scale", ctypes.c_float), ("density_threshold", ctypes.c_float)]
 
 
 class fgs_pbas_params(ctypes.Structure):

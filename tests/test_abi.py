@@ -35,10 +35,10 @@ def test_binding_covers_header_and_struct_sizes(libfgs):
     from paper_2002_00250_amd import fgs
     for n in declared_functions():
         assert hasattr(fgs, n), n
-    assert ctypes.sizeof(fgs.fgs_gmm_params) == 56
+    assert ctypes.sizeof(fgs.fgs_gmm_params) == 68
     assert ctypes.sizeof(fgs.fgs_pbas_params) == 72
     p = fgs.fgs_gmm_params_default()
-    assert p.struct_size == 56 and (p.Kc, p.Kd) == (3, 3) and p.rho_mode == 0
+    assert p.struct_size == 68 and (p.Kc, p.Kd) == (3, 3) and p.rho_mode == 0 and p.decision == 0
     q = fgs.fgs_pbas_params_default()
     assert q.struct_size == 72 and q.N == 20 and list(q.R_lower) == [18, 18, 18, 4]
 
@@ -52,7 +52,8 @@ def test_defaults_match_oracle_readings(libfgs):
     for a, b in (("alpha", "alpha"), ("lambda_", "lam"), ("T_bg", "T_bg"), ("w_init", "w_init"),
                  ("v_init_c", "v_init_c"), ("v_min_c", "v_min_c"), ("v_init_d", "v_init_d"),
                  ("v_min_d", "v_min_d"), ("w_depth", "w_depth"), ("depth_max_mm", "depth_max_mm"),
-                 ("rho_mode", "rho_mode")):
+                 ("rho_mode", "rho_mode"), ("decision", "decision"), ("density_scale", "density_scale"),
+                 ("density_threshold", "density_threshold")):
         assert np.float32(getattr(g, a)) == np.float32(getattr(og, b)), a
     q, oq = fgs.fgs_pbas_params_default(), PbasParams()
     for a in ("N", "min_matches", "R_incdec", "R_scale", "T_inc", "T_dec", "T_lower", "T_upper",
@@ -83,12 +84,19 @@ def test_errors_without_device(libfgs):
     with pytest.raises(fgs.FgsError) as e:
         fgs.fgs_create(fgs.FGS_GMM, 8, 8, g)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG
-    # the adjoint is derived for rho = alpha
-    g = fgs.fgs_gmm_params_default()
-    g.rho_mode = 1
-    with pytest.raises(fgs.FgsError) as e:
-        fgs.fgs_gmm_window_create(8, 4, 4, g)
-    assert e.value.status == fgs.FGS_ERR_UNSUPPORTED
+    for field, bad in (("decision", 2), ("density_scale", 0.0), ("density_threshold", -1.0)):
+        g = fgs.fgs_gmm_params_default()
+        setattr(g, field, bad)
+        with pytest.raises(fgs.FgsError) as e:
+            fgs.fgs_create(fgs.FGS_GMM, 8, 8, g)
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG, field
+    # the adjoint is derived for rho = alpha and the Z score
+    for field in ("rho_mode", "decision"):
+        g = fgs.fgs_gmm_params_default()
+        setattr(g, field, 1)
+        with pytest.raises(fgs.FgsError) as e:
+            fgs.fgs_gmm_window_create(8, 4, 4, g)
+        assert e.value.status == fgs.FGS_ERR_UNSUPPORTED, field
     # NULL handles are refused before any device work
     for call in (lambda: fgs.fgs_eval_accumulate(0, 0, 16, fgs.FGS_MEM_HOST),
                  lambda: fgs.fgs_eval_read(0),

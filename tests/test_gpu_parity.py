@@ -34,6 +34,7 @@ def _gmm_params_c(p: GmmParams):
     c.v_init_c, c.v_min_c, c.v_init_d, c.v_min_d = p.v_init_c, p.v_min_c, p.v_init_d, p.v_min_d
     c.w_depth, c.depth_max_mm = p.w_depth, p.depth_max_mm
     c.rho_mode = p.rho_mode
+    c.decision, c.density_scale, c.density_threshold = p.decision, p.density_scale, p.density_threshold
     return c
 
 
@@ -142,6 +143,19 @@ def test_gmm_parity_rho_over_w(Kc, Kd, alpha):
     log(f"gmm rho=alpha/w K={Kc}/{Kd} alpha={alpha}: mask diff {diff}/{total}, state bad {bad}, "
         f"not bit-equal {neq}")
     assert diff == 0 and bad == 0 and neq == 0
+
+
+@pytest.mark.parametrize("Kc,Kd,rho_mode,tau", [(3, 3, 0, 1.0), (5, 5, 1, 1.0), (7, 3, 0, 50.0)])
+def test_gmm_parity_density_decision(Kc, Kd, rho_mode, tau):
+    # decision from the scaled Eq. (1) factors: exp is not correctly rounded on either side,
+    # so masks may differ where the product sits within an ulp of the threshold (tolerance
+    # MASK_TOL); the model state does not depend on the decision and stays bit-exact.
+    cfg = preset("gmm_320x240", H=61, W=97, n_objects=3, camouflage=True)
+    p = GmmParams(Kc=Kc, Kd=Kd, rho_mode=rho_mode, decision=1, density_threshold=tau)
+    diff, total, n, bad, neq = _run_gmm_pair(cfg, p, 40)
+    log(f"gmm density decision K={Kc}/{Kd} rho_mode={rho_mode} tau={tau}: mask diff {diff}/{total}, "
+        f"state bad {bad}, not bit-equal {neq}")
+    assert diff <= MASK_TOL * total and bad == 0 and neq == 0
 
 
 def test_gmm_legacy_params_struct_means_rho_alpha():
