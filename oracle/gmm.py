@@ -38,10 +38,13 @@ depth term is present (else the single factor), and the pixel is foreground when
 P < tau.  Parity unpinned beyond its agreement with the log-sum rule when tau is
 set from equal variances (tests).
 
-Update rate of the matched mean and variance (R-06 and its variant): rho = alpha
+Update rate of the matched mean and variance (R-06 and its variants): rho = alpha
 (``rho_mode`` 0), or rho = alpha / w_k* with w_k* the matched weight after its
 update and before renormalisation (``rho_mode`` 1; the rule of OpenCV's mixture
-model, which Sec. 3.1 names as a basis of the authors' GMM).
+model, which Sec. 3.1 names as a basis of the authors' GMM), or rho = alpha * eta
+with eta the Eq. (1) density of the matched Gaussian at the sample,
+exp(-q/2) / (2 pi v) before its update (``rho_mode`` 2; Stauffer-Grimson's own
+rate).
 
 Per-pixel step (both models; X is the model's input vector, C its channel
 count, a = 1 - alpha, rho as above, lam2 = lambda*lambda):
@@ -92,7 +95,7 @@ class GmmParams:
     v_min_d: float = 1.0      # 1 depth code (about 4 cm, Sec. 4.2)
     w_depth: float = 1.0
     depth_max_mm: int = DEPTH_MAX_MM
-    rho_mode: int = 0          # 0: rho = alpha; 1: rho = alpha / w (matched, updated)
+    rho_mode: int = 0          # 0: alpha; 1: alpha / w (matched, updated); 2: alpha * eta
     decision: int = 0          # 0: Z = (d_c - lam^2) + w_d (d_d - lam^2) >= 0; 1: P < tau
     density_scale: float = 10000.0   # s (Sec. 3.1 default)
     density_threshold: float = 1.0   # tau
@@ -174,7 +177,7 @@ def first_match(w: np.ndarray, q: np.ndarray, lam2) -> np.ndarray:
 
 
 def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarray,
-                   alpha, lam2, w_init, v_init, v_min, rho_over_w: bool = False) -> Mixture:
+                   alpha, lam2, w_init, v_init, v_min, rho_mode: int = 0) -> Mixture:
     """Stauffer-Grimson update + replacement + renormalisation + ranking where ``active``."""
     f = mix.w.dtype.type
     K, C = mix.mu.shape[0], mix.mu.shape[1]
@@ -188,7 +191,13 @@ def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarra
         hit = matched & (ks == k)
         w[k] = np.where(hit, a * mix.w[k] + alpha, a * mix.w[k])
         # rho is used only where hit (there w >= alpha > 0)
-        rho = alpha / np.where(hit, w[k], f(1)) if rho_over_w else alpha
+        if rho_mode == 1:
+            rho = alpha / np.where(hit, w[k], f(1))
+        elif rho_mode == 2:
+            with np.errstate(under="ignore"):
+                rho = alpha * (np.exp(f(-0.5) * q[k]) / (f(2.0 * np.pi) * mix.v[k]))
+        else:
+            rho = alpha
         mu_new = np.empty_like(mix.mu[k])
         for c in range(C):
             mu_new[c] = mix.mu[k, c] + rho * (X[c] - mix.mu[k, c])
@@ -280,11 +289,11 @@ class GmmRef:
         self.last_has_term = has_term
 
         ones = np.ones((self.H, self.W), np.bool_)
-        rw = self.p.rho_mode == 1
+        rm = self.p.rho_mode
         self.colour = update_mixture(self.colour, Xc, qc, ones, c["alpha"], lam2, c["w_init"],
-                                     c["v_init_c"], c["v_min_c"], rw)
+                                     c["v_init_c"], c["v_min_c"], rm)
         self.depth = update_mixture(self.depth, Xd, qd, valid, c["alpha"], lam2, c["w_init"],
-                                    c["v_init_d"], c["v_min_d"], rw)
+                                    c["v_init_d"], c["v_min_d"], rm)
         self.t += 1
         return mask
 

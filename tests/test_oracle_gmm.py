@@ -458,3 +458,21 @@ def test_density_decision_uses_the_gaussian_attaining_delta():
                    [0], [0], [25])
     g.step(np.array(X, np.uint8).reshape(1, 1, 3), np.zeros((1, 1), np.uint16))
     np.testing.assert_allclose(float(g.last_P[0, 0]), 10000.0 / (2 * np.pi * 33.0), rtol=2e-6)
+
+
+def test_rho_alpha_eta_closed_form_on_a_constant_scene():
+    # Stauffer-Grimson's rate rho = alpha * eta(X | mu, v) with eta = exp(-q/2) / (2 pi v)
+    # (Eq. (1)).  A constant frame on the mean of the only colour Gaussian keeps q = 0, so
+    # rho_t = alpha / (2 pi v_t) and the variance follows v_{t+1} = v_t (1 - alpha / (2 pi v_t))
+    # = v_t - alpha / (2 pi): it falls by exactly alpha/(2 pi) per frame until the floor
+    # (rho = alpha would give v_t = (1 - alpha)^t v_0 instead).
+    alpha, v0 = 0.05, 30.0
+    p = _params(Kc=3, Kd=1, alpha=alpha, rho_mode=2, v_min_c=12.0)
+    X = [77, 88, 99]
+    g = _row_model(p, 1, [1, 0, 0], [X, [0, 0, 0], [0, 0, 0]], [v0, 675, 675], [0], [0], [25],
+                   dtype=np.float64)
+    rgb = np.array(X, np.uint8).reshape(1, 1, 3)
+    for t in range(1, 60):
+        g.step(rgb, np.zeros((1, 1), np.uint16))
+        v = float(g.state_planes()["v_c"][0, 0, 0])
+        np.testing.assert_allclose(v, max(v0 - t * alpha / (2 * np.pi), 12.0), rtol=1e-12)
