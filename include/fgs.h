@@ -87,7 +87,11 @@ typedef struct fgs_gmm_params {
     int32_t rho_mode;     /* rate of the matched mean and variance: 0 rho = alpha;
                              1 rho = alpha / w, w the matched weight after its update and
                              before renormalisation (OpenCV's mixture rule, which Sec. 3.1
-                             names as a basis). */
+                             names as a basis); 2 rho = alpha * eta, eta = exp(-q/2) /
+                             (2 pi v) the Eq. (1) density of the matched Gaussian at the
+                             sample before its update (Stauffer-Grimson's rate; exp is not
+                             correctly rounded, so results agree with other implementations
+                             to rounding, not bit for bit) */
     int32_t decision;     /* 0: the Z rule above; 1: the literal Eq. (1) factors: per model
                              P_m = density_scale * exp(-delta_m/2) / (2 pi v), v the variance
                              of the background Gaussian attaining delta_m, P = P_c * P_d where

@@ -23,7 +23,7 @@ bool gmm_supported(int Kc, int Kd);
 struct GmmConsts {
     float alpha, lam, T_bg, w_init, v_init_c, v_min_c, v_init_d, v_min_d, w_depth;
     uint32_t depth_max_mm;
-    int32_t rho_over_w;  // 1: matched-Gaussian rate alpha / w
+    int32_t rho_mode;    // matched-Gaussian rate: 0 alpha, 1 alpha / w, 2 alpha * eta
     int32_t decision;    // 1: scaled Eq. (1) density product below density_threshold
     float density_scale, density_threshold;
 };

@@ -39,7 +39,7 @@ template <int K, int C, bool REC>
 __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
                                              float alpha, float lam2, float T_bg, float w_init,
                                              float v_init, float v_min, bool& used,
-                                             float& delta, MixRec* rec, bool rho_over_w = false,
+                                             float& delta, MixRec* rec, int rho_mode = 0,
                                              uint32_t* chg = nullptr, float* vsel = nullptr) {
     if (chg) *chg = 0u;
     float q[K];
@@ -111,15 +111,20 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
         m.w[k] = wk;
     }
     if (ks >= 0) {
-        // rate of the matched mean and variance: alpha, or alpha over the matched
-        // weight just updated (>= alpha > 0)
+        // rate of the matched mean and variance: alpha; alpha over the matched weight
+        // just updated (>= alpha > 0); or alpha times the Eq. (1) density of the
+        // matched Gaussian at the sample, before its update
         float rho = alpha;
-        if (rho_over_w) {
-            float wm = m.w[0];
+        if (rho_mode != 0) {
+            float wm = m.w[0], qm = q[0], vm = m.v[0];
 #pragma unroll
             for (int k = 1; k < K; ++k)
-                if (k == ks) wm = m.w[k];
-            rho = alpha / wm;
+                if (k == ks) {
+                    wm = m.w[k];
+                    qm = q[k];
+                    vm = m.v[k];
+                }
+            rho = rho_mode == 1 ? alpha / wm : alpha * (expf(-0.5f * qm) / (6.28318530717958647692f * vm));
         }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -258,7 +263,7 @@ __device__ __forceinline__ float density_factor(float delta, float v, float s) {
 
 // One pixel of one frame: ingest, both mixtures' classify-and-update, the
 // combined decision, the mask, and the state write-back.  RW selects the rate of
-// the matched mean and variance: 0 alpha, 1 alpha / w, 2 as a.c.rho_over_w says;
+// the matched mean and variance: 0 alpha, 1 as a.c.rho_mode says;
 // DEC the decision: 0 the Z rule, 1 the density product, 2 as a.c.decision says
 // (a compile-time choice keeps the other path's registers out of the kernel).
 // A plane is stored only when some lane of the wavefront may have changed it
@@ -311,7 +316,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     float dc, dd;
     uint32_t chg_c, chg_d;
     float vsel_c = 1.0f, vsel_d = 1.0f;
-    const bool rw = RW == 2 ? a.c.rho_over_w != 0 : RW == 1;
+    const int rw = RW == 0 ? 0 : a.c.rho_mode;
     const bool dec = DEC == 2 ? a.c.decision != 0 : DEC == 1;
     float4* so = a.state;
     mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,

@@ -112,7 +112,7 @@ void launch_step_g(const GmmStepArgs& a, unsigned grid, hipStream_t s) {
 template <int KC, int KD>
 hipError_t launch_step_t(const GmmStepArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)((a.npix + kBlock - 1) / kBlock);
-    if (a.c.rho_over_w || a.c.decision) launch_step_g<KC, KD, true>(a, grid, s);
+    if (a.c.rho_mode || a.c.decision) launch_step_g<KC, KD, true>(a, grid, s);
     else launch_step_g<KC, KD, false>(a, grid, s);
     return hipGetLastError();
 }

@@ -105,7 +105,7 @@ fgs_status check_gmm(const fgs_gmm_params& p) {
     if (p.struct_size != sizeof(fgs_gmm_params))
         return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u != %zu", p.struct_size,
                     sizeof(fgs_gmm_params));
-    if (p.rho_mode != 0 && p.rho_mode != 1) return fail(FGS_ERR_INVALID_ARG, "rho_mode %d not 0 or 1", p.rho_mode);
+    if (p.rho_mode < 0 || p.rho_mode > 2) return fail(FGS_ERR_INVALID_ARG, "rho_mode %d not 0, 1 or 2", p.rho_mode);
     if (p.decision != 0 && p.decision != 1) return fail(FGS_ERR_INVALID_ARG, "decision %d not 0 or 1", p.decision);
     if (!(p.density_scale > 0.f && p.density_scale < INFINITY) ||
         !(p.density_threshold >= 0.f && p.density_threshold < INFINITY))
@@ -177,7 +177,7 @@ fgs_status fgs::load_gmm_params(const void* src, fgs_gmm_params* p) {
 GmmConsts fgs::gmm_consts(const fgs_gmm_params& p) {
     return GmmConsts{p.alpha,    p.lambda,   p.T_bg,    p.w_init,
                      p.v_init_c, p.v_min_c,  p.v_init_d, p.v_min_d,
-                     p.w_depth,  (uint32_t)p.depth_max_mm, p.rho_mode == 1 ? 1 : 0,
+                     p.w_depth,  (uint32_t)p.depth_max_mm, p.rho_mode,
                      p.decision == 1 ? 1 : 0, p.density_scale, p.density_threshold};
 }
 

@@ -80,7 +80,7 @@ def test_errors_without_device(libfgs):
         fgs.fgs_create(fgs.FGS_GMM, 8, 8, g)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG and "struct_size 53" in str(e.value)
     g = fgs.fgs_gmm_params_default()
-    g.rho_mode = 2
+    g.rho_mode = 3
     with pytest.raises(fgs.FgsError) as e:
         fgs.fgs_create(fgs.FGS_GMM, 8, 8, g)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG
