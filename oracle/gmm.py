@@ -30,6 +30,17 @@ What the paper fixes (Sec. 3.1) and what is read in
   With no valid depth (or w_d = 0) this is exactly the Stauffer-Grimson test
   "the pixel matches none of the background Gaussians".
 
+Variance variant (``var_mode`` 1; R-05 keeps one isotropic variance): the other
+reading of Sec. 3.1's remark that independent colour components allow three
+variances instead of a covariance matrix.  Each colour Gaussian has a variance per
+channel; q_k = ((e_0^2/v_0 + e_1^2/v_1) + e_2^2/v_2), each term rounded as
+written (the squared Mahalanobis distance), matched when q_k < lambda^2; each
+channel's variance follows its own squared deviation from the new mean and is
+floored on its own; new Gaussians start, and variances are floored, at one third of
+the isotropic constants (the isotropic v is the sum of the three); the rank key is
+w / sqrt((v_0 + v_1) + v_2), and where a single variance is needed (the Eq. (1)
+density) it is that sum.  The depth model has one channel and is unchanged.
+
 Decision variant (``decision`` 1; R-09 keeps the exponent terms only): each model's
 factor is Eq. (1) scaled by s for the background Gaussian that attains delta_m,
 P_m = s * exp(-delta_m / 2) / (2 pi v), v that Gaussian's variance (binary32 in
@@ -99,6 +110,7 @@ class GmmParams:
     decision: int = 0          # 0: Z = (d_c - lam^2) + w_d (d_d - lam^2) >= 0; 1: P < tau
     density_scale: float = 10000.0   # s (Sec. 3.1 default)
     density_threshold: float = 1.0   # tau
+    var_mode: int = 0          # 0: one variance per colour Gaussian; 1: one per channel
 
 
 @dataclass
@@ -115,6 +127,36 @@ class Mixture:
 def fresh_mixture(K: int, C: int, H: int, W: int, v_init, dtype) -> Mixture:
     return Mixture(np.zeros((K, H, W), dtype), np.zeros((K, C, H, W), dtype),
                    np.full((K, H, W), v_init, dtype))
+
+
+def fresh_mixture_diag(K: int, C: int, H: int, W: int, v_init, dtype) -> Mixture:
+    """A mixture with a variance per channel: v [K,C,H,W]."""
+    return Mixture(np.zeros((K, H, W), dtype), np.zeros((K, C, H, W), dtype),
+                   np.full((K, C, H, W), v_init, dtype))
+
+
+def mahalanobis_sq(mix: Mixture, X: np.ndarray) -> np.ndarray:
+    """q[k] = sum over channels, in channel order, of (X - mu_k)^2 / v_k (per-channel v)."""
+    K, C = mix.mu.shape[0], mix.mu.shape[1]
+    q = np.empty((K,) + X.shape[1:], X.dtype)
+    for k in range(K):
+        e = X[0] - mix.mu[k, 0]
+        acc = (e * e) / mix.v[k, 0]
+        for c in range(1, C):
+            e = X[c] - mix.mu[k, c]
+            acc = acc + (e * e) / mix.v[k, c]
+        q[k] = acc
+    return q
+
+
+def variance_sum(v: np.ndarray) -> np.ndarray:
+    """The single variance of a Gaussian: v itself, or ((v_0 + v_1) + ...) if per channel."""
+    if v.ndim == 3:
+        return v
+    acc = v[:, 0]
+    for c in range(1, v.shape[1]):
+        acc = acc + v[:, c]
+    return acc
 
 
 def sq_distances(mix: Mixture, X: np.ndarray) -> np.ndarray:
@@ -181,6 +223,8 @@ def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarra
     """Stauffer-Grimson update + replacement + renormalisation + ranking where ``active``."""
     f = mix.w.dtype.type
     K, C = mix.mu.shape[0], mix.mu.shape[1]
+    diag = mix.v.ndim == 4          # a variance per channel
+    vsum = variance_sum(mix.v)
     a = f(1) - alpha
     ks = first_match(mix.w, q, lam2)
     matched = ks >= 0
@@ -195,38 +239,45 @@ def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarra
             rho = alpha / np.where(hit, w[k], f(1))
         elif rho_mode == 2:
             with np.errstate(under="ignore"):
-                rho = alpha * (np.exp(f(-0.5) * q[k]) / (f(2.0 * np.pi) * mix.v[k]))
+                rho = alpha * (np.exp(f(-0.5) * q[k]) / (f(2.0 * np.pi) * vsum[k]))
         else:
             rho = alpha
         mu_new = np.empty_like(mix.mu[k])
         for c in range(C):
             mu_new[c] = mix.mu[k, c] + rho * (X[c] - mix.mu[k, c])
-        e = X[0] - mu_new[0]
-        d2n = e * e
-        for c in range(1, C):
-            e = X[c] - mu_new[c]
-            d2n = d2n + e * e
-        v_new = mix.v[k] + rho * (d2n - mix.v[k])
-        v_new = np.maximum(v_new, v_min)
+        if diag:
+            v_new = np.empty_like(mix.v[k])
+            for c in range(C):
+                e = X[c] - mu_new[c]
+                v_new[c] = np.maximum(mix.v[k, c] + rho * (e * e - mix.v[k, c]), v_min)
+            v[k] = np.where(hit[None], v_new, mix.v[k])
+        else:
+            e = X[0] - mu_new[0]
+            d2n = e * e
+            for c in range(1, C):
+                e = X[c] - mu_new[c]
+                d2n = d2n + e * e
+            v_new = mix.v[k] + rho * (d2n - mix.v[k])
+            v_new = np.maximum(v_new, v_min)
+            v[k] = np.where(hit, v_new, mix.v[k])
         mu[k] = np.where(hit[None], mu_new, mix.mu[k])
-        v[k] = np.where(hit, v_new, mix.v[k])
     # No match: the last-ranked Gaussian is replaced by a new one centred on X.
     rep = ~matched
     w[K - 1] = np.where(rep, w_init, w[K - 1])
     mu[K - 1] = np.where(rep[None], X, mu[K - 1])
-    v[K - 1] = np.where(rep, v_init, v[K - 1])
+    v[K - 1] = np.where(rep[None] if diag else rep, v_init, v[K - 1])
     # Renormalise (sequential sum) and rank by omega/sigma (stable, descending).
     S = w[0].copy()
     for k in range(1, K):
         S = S + w[k]
     w = w / S[None]
-    key = w / np.sqrt(v)
+    key = w / np.sqrt(variance_sum(v))
     order = np.argsort(-key, axis=0, kind="stable")
     w = np.take_along_axis(w, order, axis=0)
-    v = np.take_along_axis(v, order, axis=0)
+    v = np.take_along_axis(v, order[:, None] if diag else order, axis=0)
     mu = np.take_along_axis(mu, order[:, None], axis=0)
     out = Mixture(np.where(active[None], w, mix.w), np.where(active[None, None], mu, mix.mu),
-                  np.where(active[None], v, mix.v))
+                  np.where(active[None, None] if diag else active[None], v, mix.v))
     return out
 
 
@@ -238,7 +289,10 @@ class GmmRef:
         self.H, self.W = H, W
         self.dtype = np.dtype(dtype)
         f = self.dtype.type
-        self.colour = fresh_mixture(self.p.Kc, 3, H, W, f(self.p.v_init_c), self.dtype)
+        if self.p.var_mode == 1:
+            self.colour = fresh_mixture_diag(self.p.Kc, 3, H, W, f(self.p.v_init_c) / f(3), self.dtype)
+        else:
+            self.colour = fresh_mixture(self.p.Kc, 3, H, W, f(self.p.v_init_c), self.dtype)
         self.depth = fresh_mixture(self.p.Kd, 1, H, W, f(self.p.v_init_d), self.dtype)
         self.t = 0
         self.last_Z = None
@@ -260,7 +314,8 @@ class GmmRef:
         Xd = depth_q8(depth, self.p.depth_max_mm).astype(self.dtype)[None]     # [1,H,W]
         valid = depth_valid(depth)
 
-        qc = sq_distances(self.colour, Xc) / self.colour.v
+        diag = self.p.var_mode == 1
+        qc = mahalanobis_sq(self.colour, Xc) if diag else sq_distances(self.colour, Xc) / self.colour.v
         qd = sq_distances(self.depth, Xd) / self.depth.v
 
         # Decision on the pre-update (ranked) models.
@@ -275,7 +330,7 @@ class GmmRef:
         Z = np.where(term_c, np.where(term_d, tc + td, tc), td)
         has_term = term_c | term_d
         if self.p.decision == 1:
-            vc = np.take_along_axis(self.colour.v, kc[None], axis=0)[0]
+            vc = np.take_along_axis(variance_sum(self.colour.v), kc[None], axis=0)[0]
             vd = np.take_along_axis(self.depth.v, kd[None], axis=0)[0]
             with np.errstate(over="ignore", under="ignore"):
                 Pc = density_factor(dc, vc, self.p.density_scale)
@@ -290,8 +345,9 @@ class GmmRef:
 
         ones = np.ones((self.H, self.W), np.bool_)
         rm = self.p.rho_mode
+        vi_c, vm_c = (c["v_init_c"] / f(3), c["v_min_c"] / f(3)) if diag else (c["v_init_c"], c["v_min_c"])
         self.colour = update_mixture(self.colour, Xc, qc, ones, c["alpha"], lam2, c["w_init"],
-                                     c["v_init_c"], c["v_min_c"], rm)
+                                     vi_c, vm_c, rm)
         self.depth = update_mixture(self.depth, Xd, qd, valid, c["alpha"], lam2, c["w_init"],
                                     c["v_init_d"], c["v_min_d"], rm)
         self.t += 1

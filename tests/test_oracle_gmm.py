@@ -476,3 +476,46 @@ def test_rho_alpha_eta_closed_form_on_a_constant_scene():
         g.step(rgb, np.zeros((1, 1), np.uint16))
         v = float(g.state_planes()["v_c"][0, 0, 0])
         np.testing.assert_allclose(v, max(v0 - t * alpha / (2 * np.pi), 12.0), rtol=1e-12)
+
+
+def test_per_channel_variances_reduce_to_isotropic_on_grey_input():
+    # Grey input (R = G = B) keeps every mean grey and every channel deviation equal, so a
+    # per-channel model whose variances start at v_init/3 and whose threshold is 3 lambda^2
+    # is the isotropic model in other units: q_diag = 3 q_iso, v_c = v_iso / 3 per channel,
+    # identical weights, means, ranking and masks (no depth; fp64).
+    rng = np.random.default_rng(11)
+    H, W, T = 6, 40, 50
+    lam = 2.5
+    iso = GmmRef(H, W, _params(Kc=3, Kd=1, lam=lam), dtype=np.float64)
+    dia = GmmRef(H, W, _params(Kc=3, Kd=1, lam=lam * np.sqrt(3.0), var_mode=1), dtype=np.float64)
+    base = rng.integers(40, 200, size=(H, W))
+    for t in range(T):
+        g = np.clip(base + rng.integers(-4, 5, size=(H, W)) + (60 if 20 <= t < 28 else 0), 0, 255)
+        g[:, : 8 + t % 5] = 255 - g[:, : 8 + t % 5]          # a moving grey object
+        rgb = np.repeat(g.astype(np.uint8)[..., None], 3, axis=-1)
+        D = np.zeros((H, W), np.uint16)
+        assert np.array_equal(iso.step(rgb, D), dia.step(rgb, D)), t
+        a, b = iso.state_planes(), dia.state_planes()
+        np.testing.assert_allclose(b["w_c"], a["w_c"], rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(b["mu_c"], a["mu_c"], rtol=1e-12)
+        for c in range(3):
+            np.testing.assert_allclose(b["v_c"][:, c], a["v_c"] / 3.0, rtol=1e-12)
+
+
+def test_per_channel_variances_decay_independently():
+    # A constant frame on the mean of the only colour Gaussian: each channel's variance
+    # decays as (1 - alpha)^t from its own start and is floored at v_min/3 on its own.
+    alpha, vmin = 0.05, 12.0
+    p = _params(Kc=2, Kd=1, alpha=alpha, v_min_c=vmin, var_mode=1)
+    X = [50, 150, 250]
+    v0 = np.array([300.0, 40.0, 4.5])
+    g = GmmRef(1, 1, p, dtype=np.float64)
+    st = dict(g.state_planes())
+    st["w_c"] = np.array([1.0, 0.0]).reshape(2, 1, 1)
+    st["mu_c"] = np.array([X, [0, 0, 0]], float).reshape(2, 3, 1, 1)
+    st["v_c"] = np.array([v0, [225.0] * 3]).reshape(2, 3, 1, 1)
+    g.set_state_planes(st)
+    for t in range(1, 80):
+        g.step(np.array(X, np.uint8).reshape(1, 1, 3), np.zeros((1, 1), np.uint16))
+        v = g.state_planes()["v_c"][0, :, 0, 0]
+        np.testing.assert_allclose(v, np.maximum((1 - alpha) ** t * v0, vmin / 3), rtol=1e-9)
