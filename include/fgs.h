@@ -99,8 +99,14 @@ typedef struct fgs_gmm_params {
                              iff P < density_threshold */
     float density_scale;  /* s of Sec. 3.1 (default 10000) */
     float density_threshold; /* decision 1 threshold (default 1) */
+    int32_t var_mode;     /* 0: one variance per colour Gaussian; 1: one per colour channel:
+                             q = sum_c (X_c - mu_c)^2 / v_c (squared Mahalanobis distance),
+                             each channel's variance updated and floored on its own, new
+                             Gaussians and floors at v_init_c / 3 and v_min_c / 3 per
+                             channel, rank key w / sqrt(v_r + v_g + v_b) */
     /* Fields after depth_max_mm were appended: a caller passing an earlier struct
-     * (struct_size 52: none of them; 56: rho_mode only) gets the defaults for the rest. */
+     * (struct_size 52: none of them; 56: rho_mode only; 68: up to density_threshold)
+     * gets the defaults for the rest. */
 } fgs_gmm_params;
 
 /*
@@ -142,8 +148,8 @@ const char* fgs_last_error(void);
 /* Fill *p with the default constants (the readings of Sec. 3.1 used by this
  * library: Kc = Kd = 3, alpha 0.01, lambda 2.5, T_bg 0.7, w_init 0.05,
  * v_init_c 675, v_min_c 12, v_init_d 25, v_min_d 1, w_depth 1, 10 m full scale,
- * rho_mode 0, decision 0, density_scale 10000, density_threshold 1).  INVALID_ARG if
- * p is NULL. */
+ * rho_mode 0, decision 0, density_scale 10000, density_threshold 1, var_mode 0).
+ * INVALID_ARG if p is NULL. */
 fgs_status fgs_gmm_params_default(fgs_gmm_params* p);
 
 /* Fill *p with the default PBAS constants (Sec. 3.2: N = 20; the rest from the
@@ -296,8 +302,9 @@ fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy);
  * theta float[3]; rgb uint8[T][H][W][3]; depth uint16[T][H][W]; Z float[T][H][W];
  * has_term uint8[T][H][W]; dZ float[T][H][W]; dtheta double[3].  The caller
  * keeps the frames unchanged between forward and backward.  `hip_stream` as in
- * fgs_create.  Errors: INVALID_ARG, UNSUPPORTED (K, or rho_mode or decision != 0:
- * the adjoint is derived for rho = alpha and the Z score), OUT_OF_MEMORY, BAD_STATE
+ * fgs_create.  Errors: INVALID_ARG, UNSUPPORTED (K, or rho_mode, decision or var_mode
+ * != 0: the adjoint is derived for rho = alpha, the Z score and one variance per
+ * Gaussian), OUT_OF_MEMORY, BAD_STATE
  * (backward or records before forward), DEVICE.
  */
 typedef struct fgs_gmm_window fgs_gmm_window;

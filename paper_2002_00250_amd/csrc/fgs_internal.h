@@ -11,13 +11,16 @@
 namespace fgs {
 
 // ---------------------------------------------------------------- GMM ----
-// Device layout: per pixel, Kc "core" float4 planes (w, mu_r, mu_g, mu_b) of the
-// colour Gaussians, then E "extra" float4 planes holding, in order, v_c[Kc],
-// w_d[Kd], mu_d[Kd], v_d[Kd] (padded).  Plane i of pixel p is at state[i*npix + p]:
-// every access is one 16-byte load or store per lane, a wavefront touching 1 KiB
-// of contiguous memory.
-inline int gmm_extra_planes(int Kc, int Kd) { return (Kc + 3 * Kd + 3) / 4; }
-inline int gmm_planes(int Kc, int Kd) { return Kc + gmm_extra_planes(Kc, Kd); }
+// Device layout: per pixel, Kc "core" float4 planes (mu_r, mu_g, mu_b, v) of the
+// colour Gaussians by rank, then E "extra" float4 planes holding, in order, the
+// floats w_c[Kc], w_d[Kd], (mu_d, v_d)[Kd] and, with per-channel colour variances,
+// (v_g, v_b)[Kc] (v in the core plane is then the red one), zero padded.  Plane i
+// of pixel p is at state[i*npix + p]: every access is one 16-byte load or store per
+// lane, a wavefront touching 1 KiB of contiguous memory.
+__host__ __device__ inline int gmm_extra_planes(int Kc, int Kd, int var_mode) {
+    return (Kc + 3 * Kd + (var_mode ? 2 * Kc : 0) + 3) / 4;
+}
+__host__ __device__ inline int gmm_planes(int Kc, int Kd, int var_mode) { return Kc + gmm_extra_planes(Kc, Kd, var_mode); }
 bool gmm_supported(int Kc, int Kd);
 
 struct GmmConsts {
@@ -26,6 +29,7 @@ struct GmmConsts {
     int32_t rho_mode;    // matched-Gaussian rate: 0 alpha, 1 alpha / w, 2 alpha * eta
     int32_t decision;    // 1: scaled Eq. (1) density product below density_threshold
     float density_scale, density_threshold;
+    int32_t var_mode;    // 1: per-channel colour variances (v_init_c, v_min_c per channel)
 };
 
 struct GmmStepArgs {
@@ -44,9 +48,9 @@ hipError_t gmm_launch_init(float4* state, int Kc, int Kd, int npix, const GmmCon
                            hipStream_t s);
 hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s);
 // canonical planar float32 <-> device layout
-hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, int npix,
+hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, int var_mode, int npix,
                              hipStream_t s);
-hipError_t gmm_launch_import(float4* state, const float* in, int Kc, int Kd, int npix,
+hipError_t gmm_launch_import(float4* state, const float* in, int Kc, int Kd, int var_mode, int npix,
                              hipStream_t s);
 
 // --------------------------------------------------------- GMM adjoint ----

@@ -12,12 +12,22 @@
 
 namespace fgs {
 
-template <int K, int C>
+// One mixture: K Gaussians over C channels.  CV = 1: one variance per Gaussian (v);
+// CV = 3: one per channel, channel 0 in v and channels 1, 2 in vx.
+template <int K, int C, int CV = 1>
 struct Mix {
     float w[K];
     float mu[K][C];
     float v[K];
+    float vx[K][CV == 3 ? 2 : 1];
 };
+
+// The single variance of Gaussian k: v, or the sum of the per-channel variances.
+template <int K, int C, int CV>
+__device__ __forceinline__ float var_sum(const Mix<K, C, CV>& m, int k) {
+    if constexpr (CV == 3) return (m.v[k] + m.vx[k][0]) + m.vx[k][1];
+    else return m.v[k];
+}
 
 // The discrete choices of one step, recorded for the adjoint: the Gaussian that
 // attains delta, the matched Gaussian (-1: replacement), whether the variance floor
@@ -35,8 +45,8 @@ struct MixRec {
 // before the step: bit r is set when the ranking moved another Gaussian to rank r
 // or when the Gaussian at rank r was matched or replaced (clear bits are certain).
 // With `vsel`, also the (pre-update) variance of the Gaussian attaining delta.
-template <int K, int C, bool REC>
-__device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], bool active,
+template <int K, int C, bool REC, int CV = 1>
+__device__ __forceinline__ void mixture_step(Mix<K, C, CV>& m, const float (&X)[C], bool active,
                                              float alpha, float lam2, float T_bg, float w_init,
                                              float v_init, float v_min, bool& used,
                                              float& delta, MixRec* rec, int rho_mode = 0,
@@ -45,14 +55,24 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
     float q[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        float e = X[0] - m.mu[k][0];
-        float d2 = e * e;
+        if constexpr (CV == 3) {  // squared Mahalanobis distance, diagonal covariance
+            float e = X[0] - m.mu[k][0];
+            float acc = (e * e) / m.v[k];
+            e = X[1] - m.mu[k][1];
+            acc = acc + (e * e) / m.vx[k][0];
+            e = X[2] - m.mu[k][2];
+            acc = acc + (e * e) / m.vx[k][1];
+            q[k] = acc;
+        } else {
+            float e = X[0] - m.mu[k][0];
+            float d2 = e * e;
 #pragma unroll
-        for (int c = 1; c < C; ++c) {
-            e = X[c] - m.mu[k][c];
-            d2 = d2 + e * e;
+            for (int c = 1; c < C; ++c) {
+                e = X[c] - m.mu[k][c];
+                d2 = d2 + e * e;
+            }
+            q[k] = d2 / m.v[k];
         }
-        q[k] = d2 / m.v[k];
     }
 
     used = m.w[0] > 0.0f;
@@ -80,10 +100,10 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
             amin = k;
         }
     if (vsel) {
-        float vs = m.v[0];
+        float vs = var_sum(m, 0);
 #pragma unroll
         for (int k = 1; k < K; ++k)
-            if (k == amin) vs = m.v[k];
+            if (k == amin) vs = var_sum(m, k);
         *vsel = vs;
     }
     if (REC) {
@@ -116,13 +136,13 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
         // matched Gaussian at the sample, before its update
         float rho = alpha;
         if (rho_mode != 0) {
-            float wm = m.w[0], qm = q[0], vm = m.v[0];
+            float wm = m.w[0], qm = q[0], vm = var_sum(m, 0);
 #pragma unroll
             for (int k = 1; k < K; ++k)
                 if (k == ks) {
                     wm = m.w[k];
                     qm = q[k];
-                    vm = m.v[k];
+                    vm = var_sum(m, k);
                 }
             rho = rho_mode == 1 ? alpha / wm : alpha * (expf(-0.5f * qm) / (6.28318530717958647692f * vm));
         }
@@ -132,25 +152,35 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
             float mn[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) mn[c] = m.mu[k][c] + rho * (X[c] - m.mu[k][c]);
-            float e = X[0] - mn[0];
-            float d2 = e * e;
+            if constexpr (CV == 3) {  // each channel's variance on its own deviation and floor
+                float e = X[0] - mn[0];
+                m.v[k] = fmaxf(m.v[k] + rho * (e * e - m.v[k]), v_min);
+                e = X[1] - mn[1];
+                m.vx[k][0] = fmaxf(m.vx[k][0] + rho * (e * e - m.vx[k][0]), v_min);
+                e = X[2] - mn[2];
+                m.vx[k][1] = fmaxf(m.vx[k][1] + rho * (e * e - m.vx[k][1]), v_min);
+            } else {
+                float e = X[0] - mn[0];
+                float d2 = e * e;
 #pragma unroll
-            for (int c = 1; c < C; ++c) {
-                e = X[c] - mn[c];
-                d2 = d2 + e * e;
+                for (int c = 1; c < C; ++c) {
+                    e = X[c] - mn[c];
+                    d2 = d2 + e * e;
+                }
+                float vn = m.v[k] + rho * (d2 - m.v[k]);
+                if (REC) rec->clamp = vn < v_min;
+                vn = fmaxf(vn, v_min);
+                m.v[k] = vn;
             }
-            float vn = m.v[k] + rho * (d2 - m.v[k]);
-            if (REC) rec->clamp = vn < v_min;
-            vn = fmaxf(vn, v_min);
 #pragma unroll
             for (int c = 0; c < C; ++c) m.mu[k][c] = mn[c];
-            m.v[k] = vn;
         }
     } else {
         m.w[K - 1] = w_init;
 #pragma unroll
         for (int c = 0; c < C; ++c) m.mu[K - 1][c] = X[c];
         m.v[K - 1] = v_init;
+        if constexpr (CV == 3) m.vx[K - 1][0] = m.vx[K - 1][1] = v_init;
     }
 
     float S = m.w[0];
@@ -166,7 +196,7 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
     int idx[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        key[k] = m.w[k] / sqrtf(m.v[k]);
+        key[k] = m.w[k] / sqrtf(var_sum(m, k));
         idx[k] = k;
     }
     // The network swaps nothing unless some adjacent pair is out of order, which in a
@@ -193,6 +223,10 @@ __device__ __forceinline__ void mixture_step(Mix<K, C>& m, const float (&X)[C], 
             }
             FGS_CSWAP(m.w[j], m.w[j - 1]);
             FGS_CSWAP(m.v[j], m.v[j - 1]);
+            if constexpr (CV == 3) {
+                FGS_CSWAP(m.vx[j][0], m.vx[j - 1][0]);
+                FGS_CSWAP(m.vx[j][1], m.vx[j - 1][1]);
+            }
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 FGS_CSWAP(m.mu[j][c], m.mu[j - 1][c]);
@@ -240,19 +274,24 @@ __device__ __forceinline__ void st_state(float4* p, float4 v) {
 }
 
 // Device layout of a GMM model (planes of npix float4, plane-major):
-//   core plane k (k < Kc):  (mu_r, mu_g, mu_b, v) of colour rank k;
+//   core plane k (k < Kc):  (mu_r, mu_g, mu_b, v) of colour rank k (with per-channel
+//   colour variances, CV = 3: v is the red one);
 //   extra planes (E of them): the floats w_c[0..Kc-1], w_d[0..Kd-1], then
-//   (mu_d, v_d) of depth rank 0, 1, ..., packed four to a plane, zero padded.
+//   (mu_d, v_d) of depth rank 0, 1, ..., then (CV = 3) the (v_g, v_b) of colour
+//   rank 0, 1, ..., packed four to a plane, zero padded.
 // Weights decay every frame, but a rank's mean and variance change only when its
 // Gaussian is matched, replaced or moved by the ranking, so the planes that hold
 // only means and variances can often be left unwritten.
-template <int KC, int KD>
+template <int KC, int KD, int CV = 1>
 struct GmmLayout {
-    static constexpr int E = (KC + 3 * KD + 3) / 4;  // extra planes
+    static constexpr int NX = KC + 3 * KD + (CV == 3 ? 2 * KC : 0);  // extra floats
+    static constexpr int E = (NX + 3) / 4;                            // extra planes
     static constexpr int w_c(int k) { return k; }
     static constexpr int w_d(int k) { return KC + k; }
     static constexpr int mu_d(int k) { return KC + KD + 2 * k; }
     static constexpr int v_d(int k) { return KC + KD + 2 * k + 1; }
+    static constexpr int v_g(int k) { return KC + 3 * KD + 2 * k; }
+    static constexpr int v_b(int k) { return KC + 3 * KD + 2 * k + 1; }
 };
 
 // Scaled Eq. (1) factor of the Gaussian attaining delta (decision 1), in the order
@@ -268,9 +307,9 @@ __device__ __forceinline__ float density_factor(float delta, float v, float s) {
 // (a compile-time choice keeps the other path's registers out of the kernel).
 // A plane is stored only when some lane of the wavefront may have changed it
 // (the skip is wavefront-uniform, so every store still covers whole lines).
-template <int KC, int KD, bool NT, int RW = 2, int DEC = 2>
+template <int KC, int KD, bool NT, int RW = 2, int DEC = 2, int CV = 1>
 __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
-    using L = GmmLayout<KC, KD>;
+    using L = GmmLayout<KC, KD, CV>;
     constexpr int E = L::E;
     const int y = p / a.W;
     const int x = p - y * a.W;
@@ -294,7 +333,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
         ex[4 * e + 2] = f.z;
         ex[4 * e + 3] = f.w;
     }
-    Mix<KC, 3> mc;
+    Mix<KC, 3, CV> mc;
     Mix<KD, 1> md;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
@@ -303,6 +342,10 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
         mc.mu[k][1] = core[k].y;
         mc.mu[k][2] = core[k].z;
         mc.v[k] = core[k].w;
+        if constexpr (CV == 3) {
+            mc.vx[k][0] = ex[L::v_g(k)];
+            mc.vx[k][1] = ex[L::v_b(k)];
+        }
     }
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
@@ -319,7 +362,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     const int rw = RW == 0 ? 0 : a.c.rho_mode;
     const bool dec = DEC == 2 ? a.c.decision != 0 : DEC == 1;
     float4* so = a.state;
-    mixture_step<KC, 3, false>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
+    mixture_step<KC, 3, false, CV>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
                                a.c.v_min_c, used_c, dc, nullptr, rw, &chg_c, DEC ? &vsel_c : nullptr);
     // the colour means and variances are final: store them before the depth step
 #pragma unroll
@@ -349,7 +392,13 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     // is updated every frame), the depth weights where depth > 0 (the depth mixture
     // is updated only there), a depth mean and variance as the depth mixture reports.
 #pragma unroll
-    for (int k = 0; k < KC; ++k) ex[L::w_c(k)] = mc.w[k];
+    for (int k = 0; k < KC; ++k) {
+        ex[L::w_c(k)] = mc.w[k];
+        if constexpr (CV == 3) {
+            ex[L::v_g(k)] = mc.vx[k][0];
+            ex[L::v_b(k)] = mc.vx[k][1];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < KD; ++k) {
         ex[L::w_d(k)] = md.w[k];
@@ -364,6 +413,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
             if (i < KC) ch = true;
             else if (i < KC + KD) ch = ch || valid;
             else if (i < KC + 3 * KD) ch = ch || ((chg_d >> ((i - KC - KD) >> 1)) & 1u);
+            else if (i < L::NX) ch = ch || ((chg_c >> ((i - KC - 3 * KD) >> 1)) & 1u);
         }
         if (__any(ch))
             st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,

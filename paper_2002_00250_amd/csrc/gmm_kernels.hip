@@ -27,19 +27,21 @@ namespace {
 constexpr int kBlock = 256;
 
 // GEN = false: the default rate and decision compiled in; GEN = true: both read
-// from the constants (any other choice).
-template <int KC, int KD, bool NT, bool GEN>
+// from the constants (any other choice).  CV = 3: per-channel colour variances.
+template <int KC, int KD, bool NT, bool GEN, int CV>
 __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p < a.npix) gmm_pixel<KC, KD, NT, GEN ? 2 : 0, GEN ? 2 : 0>(a, p);
+    if (p < a.npix) gmm_pixel<KC, KD, NT, GEN ? 2 : 0, GEN ? 2 : 0, CV>(a, p);
 }
 
 // Index of a float among the extra planes (the layout of gmm_device.h, for run-time
-// Kc, Kd): w_c[k], w_d[k], then (mu_d, v_d) pairs by rank.
+// Kc, Kd): w_c[k], w_d[k], then (mu_d, v_d) pairs by rank, then (v_g, v_b) pairs.
 __device__ __forceinline__ int x_wc(int, int, int k) { return k; }
 __device__ __forceinline__ int x_wd(int Kc, int, int k) { return Kc + k; }
 __device__ __forceinline__ int x_mud(int Kc, int Kd, int k) { return Kc + Kd + 2 * k; }
 __device__ __forceinline__ int x_vd(int Kc, int Kd, int k) { return Kc + Kd + 2 * k + 1; }
+__device__ __forceinline__ int x_vg(int Kc, int Kd, int k) { return Kc + 3 * Kd + 2 * k; }
+__device__ __forceinline__ int x_vb(int Kc, int Kd, int k) { return Kc + 3 * Kd + 2 * k + 1; }
 
 __device__ __forceinline__ float* f4(float4* s, int64_t i) { return reinterpret_cast<float*>(s + i); }
 __device__ __forceinline__ const float* f4(const float4* s, int64_t i) {
@@ -52,68 +54,88 @@ __device__ __forceinline__ float xg(const float4* s, int Kc, int64_t n, int64_t 
     return f4(s, (int64_t)(Kc + idx / 4) * n + p)[idx % 4];
 }
 
-// Fresh model: w = 0, mu = 0, v = v_init (both mixtures).
-__global__ void gmm_init_kernel(float4* state, int Kc, int Kd, int npix, float v_init_c,
+// Fresh model: w = 0, mu = 0, v = v_init (both mixtures; every colour channel's
+// variance when they are per channel).
+__global__ void gmm_init_kernel(float4* state, int Kc, int Kd, int var_mode, int npix, float v_init_c,
                                 float v_init_d) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= npix) return;
     const int64_t n = npix;
-    const int E = (Kc + 3 * Kd + 3) / 4;
+    const int E = gmm_extra_planes(Kc, Kd, var_mode);
     for (int k = 0; k < Kc; ++k) state[(int64_t)k * n + p] = make_float4(0.f, 0.f, 0.f, v_init_c);
     for (int e = 0; e < E; ++e) state[(int64_t)(Kc + e) * n + p] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int k = 0; k < Kd; ++k) *xf(state, Kc, n, p, x_vd(Kc, Kd, k)) = v_init_d;
+    if (var_mode)
+        for (int k = 0; k < Kc; ++k) {
+            *xf(state, Kc, n, p, x_vg(Kc, Kd, k)) = v_init_c;
+            *xf(state, Kc, n, p, x_vb(Kc, Kd, k)) = v_init_c;
+        }
 }
 
-// Canonical order: w_c[Kc], mu_c[Kc][3], v_c[Kc], w_d[Kd], mu_d[Kd], v_d[Kd], planes of npix.
-__global__ void gmm_export_kernel(const float4* state, float* out, int Kc, int Kd, int npix) {
+// Canonical order: w_c[Kc], mu_c[Kc][3], v_c[Kc] (per-channel: v_c[Kc][3]), w_d[Kd],
+// mu_d[Kd], v_d[Kd], planes of npix.
+__global__ void gmm_export_kernel(const float4* state, float* out, int Kc, int Kd, int var_mode, int npix) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= npix) return;
     const int64_t n = npix;
+    const int nv = var_mode ? 3 : 1;
     for (int k = 0; k < Kc; ++k) {
         const float* c = f4(state, (int64_t)k * n + p);
         out[(int64_t)k * n + p] = xg(state, Kc, n, p, x_wc(Kc, Kd, k));
         for (int ch = 0; ch < 3; ++ch) out[(int64_t)(Kc + 3 * k + ch) * n + p] = c[ch];
-        out[(int64_t)(4 * Kc + k) * n + p] = c[3];
+        out[(int64_t)(4 * Kc + nv * k) * n + p] = c[3];
+        if (var_mode) {
+            out[(int64_t)(4 * Kc + nv * k + 1) * n + p] = xg(state, Kc, n, p, x_vg(Kc, Kd, k));
+            out[(int64_t)(4 * Kc + nv * k + 2) * n + p] = xg(state, Kc, n, p, x_vb(Kc, Kd, k));
+        }
     }
+    const int d0 = (4 + nv) * Kc;
     for (int k = 0; k < Kd; ++k) {
-        out[(int64_t)(5 * Kc + k) * n + p] = xg(state, Kc, n, p, x_wd(Kc, Kd, k));
-        out[(int64_t)(5 * Kc + Kd + k) * n + p] = xg(state, Kc, n, p, x_mud(Kc, Kd, k));
-        out[(int64_t)(5 * Kc + 2 * Kd + k) * n + p] = xg(state, Kc, n, p, x_vd(Kc, Kd, k));
+        out[(int64_t)(d0 + k) * n + p] = xg(state, Kc, n, p, x_wd(Kc, Kd, k));
+        out[(int64_t)(d0 + Kd + k) * n + p] = xg(state, Kc, n, p, x_mud(Kc, Kd, k));
+        out[(int64_t)(d0 + 2 * Kd + k) * n + p] = xg(state, Kc, n, p, x_vd(Kc, Kd, k));
     }
 }
 
-__global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd, int npix) {
+__global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd, int var_mode, int npix) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= npix) return;
     const int64_t n = npix;
-    const int E = (Kc + 3 * Kd + 3) / 4;
+    const int E = gmm_extra_planes(Kc, Kd, var_mode);
+    const int nv = var_mode ? 3 : 1;
     for (int e = 0; e < E; ++e) state[(int64_t)(Kc + e) * n + p] = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int k = 0; k < Kc; ++k) {
         float* c = f4(state, (int64_t)k * n + p);
         for (int ch = 0; ch < 3; ++ch) c[ch] = in[(int64_t)(Kc + 3 * k + ch) * n + p];
-        c[3] = in[(int64_t)(4 * Kc + k) * n + p];
+        c[3] = in[(int64_t)(4 * Kc + nv * k) * n + p];
         *xf(state, Kc, n, p, x_wc(Kc, Kd, k)) = in[(int64_t)k * n + p];
+        if (var_mode) {
+            *xf(state, Kc, n, p, x_vg(Kc, Kd, k)) = in[(int64_t)(4 * Kc + nv * k + 1) * n + p];
+            *xf(state, Kc, n, p, x_vb(Kc, Kd, k)) = in[(int64_t)(4 * Kc + nv * k + 2) * n + p];
+        }
     }
+    const int d0 = (4 + nv) * Kc;
     for (int k = 0; k < Kd; ++k) {
-        *xf(state, Kc, n, p, x_wd(Kc, Kd, k)) = in[(int64_t)(5 * Kc + k) * n + p];
-        *xf(state, Kc, n, p, x_mud(Kc, Kd, k)) = in[(int64_t)(5 * Kc + Kd + k) * n + p];
-        *xf(state, Kc, n, p, x_vd(Kc, Kd, k)) = in[(int64_t)(5 * Kc + 2 * Kd + k) * n + p];
+        *xf(state, Kc, n, p, x_wd(Kc, Kd, k)) = in[(int64_t)(d0 + k) * n + p];
+        *xf(state, Kc, n, p, x_mud(Kc, Kd, k)) = in[(int64_t)(d0 + Kd + k) * n + p];
+        *xf(state, Kc, n, p, x_vd(Kc, Kd, k)) = in[(int64_t)(d0 + 2 * Kd + k) * n + p];
     }
 }
 
-template <int KC, int KD, bool GEN>
+template <int KC, int KD, bool GEN, int CV>
 void launch_step_g(const GmmStepArgs& a, unsigned grid, hipStream_t s) {
     if (a.streaming)
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, GEN>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, GEN>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 template <int KC, int KD>
 hipError_t launch_step_t(const GmmStepArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)((a.npix + kBlock - 1) / kBlock);
-    if (a.c.rho_mode || a.c.decision) launch_step_g<KC, KD, true>(a, grid, s);
-    else launch_step_g<KC, KD, false>(a, grid, s);
+    if (a.c.var_mode) launch_step_g<KC, KD, true, 3>(a, grid, s);
+    else if (a.c.rho_mode || a.c.decision) launch_step_g<KC, KD, true, 1>(a, grid, s);
+    else launch_step_g<KC, KD, false, 1>(a, grid, s);
     return hipGetLastError();
 }
 
@@ -141,22 +163,22 @@ hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s) 
 hipError_t gmm_launch_init(float4* state, int Kc, int Kd, int npix, const GmmConsts& c,
                            hipStream_t s) {
     const unsigned grid = (unsigned)((npix + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(gmm_init_kernel, dim3(grid), dim3(kBlock), 0, s, state, Kc, Kd, npix,
+    hipLaunchKernelGGL(gmm_init_kernel, dim3(grid), dim3(kBlock), 0, s, state, Kc, Kd, c.var_mode, npix,
                        c.v_init_c, c.v_init_d);
     return hipGetLastError();
 }
 
-hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, int npix,
+hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, int var_mode, int npix,
                              hipStream_t s) {
     const unsigned grid = (unsigned)((npix + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(gmm_export_kernel, dim3(grid), dim3(kBlock), 0, s, state, out, Kc, Kd, npix);
+    hipLaunchKernelGGL(gmm_export_kernel, dim3(grid), dim3(kBlock), 0, s, state, out, Kc, Kd, var_mode, npix);
     return hipGetLastError();
 }
 
-hipError_t gmm_launch_import(float4* state, const float* in, int Kc, int Kd, int npix,
+hipError_t gmm_launch_import(float4* state, const float* in, int Kc, int Kd, int var_mode, int npix,
                              hipStream_t s) {
     const unsigned grid = (unsigned)((npix + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(gmm_import_kernel, dim3(grid), dim3(kBlock), 0, s, state, in, Kc, Kd, npix);
+    hipLaunchKernelGGL(gmm_import_kernel, dim3(grid), dim3(kBlock), 0, s, state, in, Kc, Kd, var_mode, npix);
     return hipGetLastError();
 }
 

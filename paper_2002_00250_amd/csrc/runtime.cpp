@@ -50,7 +50,7 @@ constexpr int64_t kMaxPixels = int64_t(1) << 28;
 
 struct StateHeader {
     uint32_t magic, version, algo;
-    int32_t H, W, A, B, reserved;
+    int32_t H, W, A, B, flags;  // flags bit 0: per-channel colour variances (GMM)
     int64_t frames;
     uint64_t seed;
     uint8_t pad[16];
@@ -91,7 +91,7 @@ fgs_status device_fail(fgs_model* m, hipError_t e, const char* what) {
     } while (0)
 
 size_t gmm_payload_bytes(const fgs_model* m) {
-    return (size_t)(5 * m->gp.Kc + 3 * m->gp.Kd) * (size_t)m->npix * 4;
+    return (size_t)((m->gp.var_mode ? 7 : 5) * m->gp.Kc + 3 * m->gp.Kd) * (size_t)m->npix * 4;
 }
 size_t pbas_payload_bytes(const fgs_model* m) {
     const size_t n = (size_t)m->npix;
@@ -107,6 +107,7 @@ fgs_status check_gmm(const fgs_gmm_params& p) {
                     sizeof(fgs_gmm_params));
     if (p.rho_mode < 0 || p.rho_mode > 2) return fail(FGS_ERR_INVALID_ARG, "rho_mode %d not 0, 1 or 2", p.rho_mode);
     if (p.decision != 0 && p.decision != 1) return fail(FGS_ERR_INVALID_ARG, "decision %d not 0 or 1", p.decision);
+    if (p.var_mode != 0 && p.var_mode != 1) return fail(FGS_ERR_INVALID_ARG, "var_mode %d not 0 or 1", p.var_mode);
     if (!(p.density_scale > 0.f && p.density_scale < INFINITY) ||
         !(p.density_threshold >= 0.f && p.density_threshold < INFINITY))
         return fail(FGS_ERR_INVALID_ARG, "density_scale must be > 0 and density_threshold >= 0, both finite");
@@ -161,24 +162,29 @@ fgs_status ensure_staging(fgs_model* m) {
 fgs_status fgs::load_gmm_params(const void* src, fgs_gmm_params* p) {
     fgs_gmm_params_default(p);
     if (!src) return FGS_OK;
-    // earlier layouts: up to depth_max_mm, then with rho_mode
+    // earlier layouts: up to depth_max_mm, then with rho_mode, then up to density_threshold
     constexpr size_t kV1 = offsetof(fgs_gmm_params, rho_mode);
     constexpr size_t kV2 = offsetof(fgs_gmm_params, decision);
+    constexpr size_t kV3 = offsetof(fgs_gmm_params, var_mode);
     uint32_t size = 0;
     std::memcpy(&size, src, sizeof size);
-    if (size != sizeof(fgs_gmm_params) && size != kV1 && size != kV2)
-        return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u is none of %zu, %zu, %zu", size,
-                    sizeof(fgs_gmm_params), kV2, kV1);
+    if (size != sizeof(fgs_gmm_params) && size != kV1 && size != kV2 && size != kV3)
+        return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u is none of %zu, %zu, %zu, %zu", size,
+                    sizeof(fgs_gmm_params), kV3, kV2, kV1);
     std::memcpy(p, src, size);  // the fields it does not cover keep their defaults
     p->struct_size = sizeof *p;
     return FGS_OK;
 }
 
 GmmConsts fgs::gmm_consts(const fgs_gmm_params& p) {
-    return GmmConsts{p.alpha,    p.lambda,   p.T_bg,    p.w_init,
-                     p.v_init_c, p.v_min_c,  p.v_init_d, p.v_min_d,
-                     p.w_depth,  (uint32_t)p.depth_max_mm, p.rho_mode,
-                     p.decision == 1 ? 1 : 0, p.density_scale, p.density_threshold};
+    // per-channel colour variances start and are floored at a third of the isotropic
+    // constants (the isotropic variance is the sum of the three)
+    const float vi = p.var_mode ? p.v_init_c / 3.0f : p.v_init_c;
+    const float vm = p.var_mode ? p.v_min_c / 3.0f : p.v_min_c;
+    return GmmConsts{p.alpha, p.lambda,   p.T_bg,    p.w_init,
+                     vi,      vm,         p.v_init_d, p.v_min_d,
+                     p.w_depth, (uint32_t)p.depth_max_mm, p.rho_mode,
+                     p.decision == 1 ? 1 : 0, p.density_scale, p.density_threshold, p.var_mode};
 }
 
 bool fgs::model_use_streaming(const fgs_model* m) {
@@ -276,6 +282,7 @@ fgs_status fgs_gmm_params_default(fgs_gmm_params* p) {
     p->decision = 0;
     p->density_scale = 10000.0f;
     p->density_threshold = 1.0f;
+    p->var_mode = 0;
     return FGS_OK;
 }
 
@@ -363,7 +370,7 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
            o_i1 = 0, o_mask = 0;
     if (algo == FGS_GMM) {
         o_state = off;
-        off += align256((size_t)gmm_planes(m->gp.Kc, m->gp.Kd) * n * 16);
+        off += align256((size_t)gmm_planes(m->gp.Kc, m->gp.Kd, m->gp.var_mode) * n * 16);
     } else {
         const size_t N = (size_t)m->pp.N;
         o_samples = off; off += align256(N * n * 4);
@@ -628,6 +635,7 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     h.W = m->W;
     h.A = m->algo == FGS_GMM ? m->gp.Kc : m->pp.N;
     h.B = m->algo == FGS_GMM ? m->gp.Kd : 0;
+    h.flags = m->algo == FGS_GMM ? m->gp.var_mode : 0;
     h.frames = m->t;
     h.seed = m->algo == FGS_PBAS ? m->pp.seed : 0;
 
@@ -639,7 +647,7 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     }
     hipError_t e = m->algo == FGS_GMM
                        ? gmm_launch_export(m->gmm_state, reinterpret_cast<float*>(target), m->gp.Kc,
-                                           m->gp.Kd, m->npix, m->stream)
+                                           m->gp.Kd, m->gp.var_mode, m->npix, m->stream)
                        : pbas_launch_export(m->pb, m->npix, m->pp.N, target, m->stream);
     if (e == hipSuccess) {
         if (where == FGS_MEM_HOST) {
@@ -674,7 +682,8 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
     const int A = m->algo == FGS_GMM ? m->gp.Kc : m->pp.N;
     const int B = m->algo == FGS_GMM ? m->gp.Kd : 0;
     if (h.magic != kStateMagic || h.version != kStateVersion || h.algo != (uint32_t)m->algo ||
-        h.H != m->H || h.W != m->W || h.A != A || h.B != B || h.frames < 0 || h.frames >= 0xFFFFFFFFll)
+        h.H != m->H || h.W != m->W || h.A != A || h.B != B || h.frames < 0 || h.frames >= 0xFFFFFFFFll ||
+        h.flags != (m->algo == FGS_GMM ? m->gp.var_mode : 0))
         return fail(FGS_ERR_INVALID_ARG, "state header does not match this model");
     if (m->algo == FGS_PBAS && h.seed != m->pp.seed)
         return fail(FGS_ERR_INVALID_ARG, "state was taken with another PBAS seed");
@@ -689,7 +698,7 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
     }
     if (e == hipSuccess)
         e = m->algo == FGS_GMM ? gmm_launch_import(m->gmm_state, reinterpret_cast<const float*>(srcp),
-                                                   m->gp.Kc, m->gp.Kd, m->npix, m->stream)
+                                                   m->gp.Kc, m->gp.Kd, m->gp.var_mode, m->npix, m->stream)
                                : pbas_launch_import(m->pb, m->npix, m->pp.N, srcp, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (tmp) (void)hipFree(tmp);
@@ -759,9 +768,9 @@ fgs_status fgs_gmm_window_create(int32_t T, int32_t H, int32_t W, const fgs_gmm_
     fgs_status st = load_gmm_params(params, &p);
     if (st == FGS_OK) st = check_gmm(p);
     if (st != FGS_OK) return st;
-    if (p.rho_mode != 0 || p.decision != 0)
-        return fail(FGS_ERR_UNSUPPORTED, "the adjoint is derived for rho = alpha and the Z score "
-                                         "(rho_mode 0, decision 0)");
+    if (p.rho_mode != 0 || p.decision != 0 || p.var_mode != 0)
+        return fail(FGS_ERR_UNSUPPORTED, "the adjoint is derived for rho = alpha, the Z score and one "
+                                         "variance per Gaussian (rho_mode, decision, var_mode 0)");
     if (p.Kc != p.Kd || !gmm_window_supported(p.Kc))
         return fail(FGS_ERR_UNSUPPORTED, "the adjoint supports Kc = Kd in 1..5, not (%d, %d)", p.Kc, p.Kd);
     if (T < 1 || H < 1 || W < 1 || (int64_t)H * W > kMaxPixels || checkpoint_every < 1)

@@ -330,6 +330,8 @@ fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, c
         fgs_gmm_params p;
         const fgs_status ls = load_gmm_params(params, &p);
         if (ls != FGS_OK) return ls;
+        if (p.var_mode != 0)
+            return fail(FGS_ERR_UNSUPPORTED, "the server runs GMM streams with one variance per Gaussian");
         if (p.Kc != s->gmm_K || p.Kd != s->gmm_K)
             return fail(FGS_ERR_UNSUPPORTED, "this server runs GMM streams with Kc = Kd = %d", s->gmm_K);
     } else if (algo == FGS_PBAS) {

@@ -45,7 +45,8 @@ class fgs_gmm_params(ctypes.Structure):
                 ("w_init", ctypes.c_float), ("v_init_c", ctypes.c_float), ("v_min_c", ctypes.c_float),
                 ("v_init_d", ctypes.c_float), ("v_min_d", ctypes.c_float), ("w_depth", ctypes.c_float),
                 ("depth_max_mm", c_int32), ("rho_mode", c_int32), ("decision", c_int32),
-                ("density_scale", ctypes.c_float), ("density_threshold", ctypes.c_float)]
+                ("density_scale", ctypes.c_float), ("density_threshold", ctypes.c_float),
+                ("var_mode", c_int32)]
 
 
 class fgs_pbas_params(ctypes.Structure):
@@ -331,7 +332,7 @@ def unpack_state(blob: np.ndarray) -> dict:
     b = np.ascontiguousarray(blob).view(np.uint8)
     hdr = b[:STATE_HEADER_BYTES]
     magic, version, algo = (int(v) for v in hdr[:12].view(np.uint32))
-    H, W, A, B = (int(v) for v in hdr[12:28].view(np.int32))
+    H, W, A, B, flags = (int(v) for v in hdr[12:32].view(np.int32))
     frames = int(hdr[32:40].view(np.int64)[0])
     seed = int(hdr[40:48].view(np.uint64)[0])
     if magic != 0x53534746:
@@ -349,9 +350,10 @@ def unpack_state(blob: np.ndarray) -> dict:
             a = f[o:o + k * n].reshape(shape)
             o += k * n
             return a
+        diag = bool(flags & 1)   # per-channel colour variances
         out.update(Kc=Kc, Kd=Kd, w_c=take(Kc, (Kc, H, W)), mu_c=take(3 * Kc, (Kc, 3, H, W)),
-                   v_c=take(Kc, (Kc, H, W)), w_d=take(Kd, (Kd, H, W)), mu_d=take(Kd, (Kd, H, W)),
-                   v_d=take(Kd, (Kd, H, W)))
+                   v_c=take(3 * Kc, (Kc, 3, H, W)) if diag else take(Kc, (Kc, H, W)),
+                   w_d=take(Kd, (Kd, H, W)), mu_d=take(Kd, (Kd, H, W)), v_d=take(Kd, (Kd, H, W)))
     else:
         N = A
         u32 = pay[:2 * N * n * 4].view(np.uint32)
@@ -368,7 +370,8 @@ def pack_state(st: dict) -> np.ndarray:
     algo = st["algo"]
     A, B = (st["Kc"], st["Kd"]) if algo == FGS_GMM else (st["N"], 0)
     hdr[:12] = np.array([0x53534746, 1, algo], np.uint32).view(np.uint8)
-    hdr[12:32] = np.array([st["H"], st["W"], A, B, 0], np.int32).view(np.uint8)
+    flags = 1 if algo == FGS_GMM and np.ndim(st["v_c"]) == 4 else 0
+    hdr[12:32] = np.array([st["H"], st["W"], A, B, flags], np.int32).view(np.uint8)
     hdr[32:40] = np.array([st["t"]], np.int64).view(np.uint8)
     hdr[40:48] = np.array([st.get("seed", 0)], np.uint64).view(np.uint8)
     if algo == FGS_GMM:

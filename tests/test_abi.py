@@ -35,10 +35,10 @@ def test_binding_covers_header_and_struct_sizes(libfgs):
     from paper_2002_00250_amd import fgs
     for n in declared_functions():
         assert hasattr(fgs, n), n
-    assert ctypes.sizeof(fgs.fgs_gmm_params) == 68
+    assert ctypes.sizeof(fgs.fgs_gmm_params) == 72
     assert ctypes.sizeof(fgs.fgs_pbas_params) == 72
     p = fgs.fgs_gmm_params_default()
-    assert p.struct_size == 68 and (p.Kc, p.Kd) == (3, 3) and p.rho_mode == 0 and p.decision == 0
+    assert p.struct_size == 72 and (p.Kc, p.Kd) == (3, 3) and (p.rho_mode, p.decision, p.var_mode) == (0, 0, 0)
     q = fgs.fgs_pbas_params_default()
     assert q.struct_size == 72 and q.N == 20 and list(q.R_lower) == [18, 18, 18, 4]
 
@@ -53,7 +53,7 @@ def test_defaults_match_oracle_readings(libfgs):
                  ("v_init_c", "v_init_c"), ("v_min_c", "v_min_c"), ("v_init_d", "v_init_d"),
                  ("v_min_d", "v_min_d"), ("w_depth", "w_depth"), ("depth_max_mm", "depth_max_mm"),
                  ("rho_mode", "rho_mode"), ("decision", "decision"), ("density_scale", "density_scale"),
-                 ("density_threshold", "density_threshold")):
+                 ("density_threshold", "density_threshold"), ("var_mode", "var_mode")):
         assert np.float32(getattr(g, a)) == np.float32(getattr(og, b)), a
     q, oq = fgs.fgs_pbas_params_default(), PbasParams()
     for a in ("N", "min_matches", "R_incdec", "R_scale", "T_inc", "T_dec", "T_lower", "T_upper",
@@ -84,14 +84,14 @@ def test_errors_without_device(libfgs):
     with pytest.raises(fgs.FgsError) as e:
         fgs.fgs_create(fgs.FGS_GMM, 8, 8, g)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG
-    for field, bad in (("decision", 2), ("density_scale", 0.0), ("density_threshold", -1.0)):
+    for field, bad in (("decision", 2), ("density_scale", 0.0), ("density_threshold", -1.0), ("var_mode", 2)):
         g = fgs.fgs_gmm_params_default()
         setattr(g, field, bad)
         with pytest.raises(fgs.FgsError) as e:
             fgs.fgs_create(fgs.FGS_GMM, 8, 8, g)
         assert e.value.status == fgs.FGS_ERR_INVALID_ARG, field
     # the adjoint is derived for rho = alpha and the Z score
-    for field in ("rho_mode", "decision"):
+    for field in ("rho_mode", "decision", "var_mode"):
         g = fgs.fgs_gmm_params_default()
         setattr(g, field, 1)
         with pytest.raises(fgs.FgsError) as e:
@@ -120,3 +120,23 @@ def test_state_pack_unpack_roundtrip():
     for k in ("samples", "dhist", "R", "T", "S"):
         np.testing.assert_array_equal(back[k], st[k])
     assert back["t"] == 42 and back["seed"] == 7
+
+
+@pytest.mark.parametrize("diag", [False, True])
+def test_gmm_state_pack_unpack_flags(diag):
+    # GMM blobs: header flag bit 0 marks per-channel colour variances ([Kc][3] planes)
+    import numpy as np
+    from paper_2002_00250_amd import fgs
+    rng = np.random.default_rng(1)
+    Kc, Kd, H, W = 3, 2, 4, 6
+    st = dict(algo=fgs.FGS_GMM, H=H, W=W, t=9, Kc=Kc, Kd=Kd,
+              w_c=rng.random((Kc, H, W), dtype=np.float32), mu_c=rng.random((Kc, 3, H, W), dtype=np.float32),
+              v_c=rng.random((Kc, 3, H, W) if diag else (Kc, H, W), dtype=np.float32),
+              w_d=rng.random((Kd, H, W), dtype=np.float32), mu_d=rng.random((Kd, H, W), dtype=np.float32),
+              v_d=rng.random((Kd, H, W), dtype=np.float32))
+    blob = fgs.pack_state(st)
+    assert blob.size == fgs.STATE_HEADER_BYTES + 4 * H * W * ((7 if diag else 5) * Kc + 3 * Kd)
+    assert int(blob[28:32].view(np.int32)[0]) == (1 if diag else 0)
+    back = fgs.unpack_state(blob)
+    for k in ("w_c", "mu_c", "v_c", "w_d", "mu_d", "v_d"):
+        np.testing.assert_array_equal(back[k], st[k])

@@ -35,6 +35,7 @@ def _gmm_params_c(p: GmmParams):
     c.w_depth, c.depth_max_mm = p.w_depth, p.depth_max_mm
     c.rho_mode = p.rho_mode
     c.decision, c.density_scale, c.density_threshold = p.decision, p.density_scale, p.density_threshold
+    c.var_mode = p.var_mode
     return c
 
 
@@ -166,6 +167,56 @@ def test_gmm_parity_rho_alpha_eta():
     diff, total, n, bad, neq = _run_gmm_pair(cfg, p, 40)
     log(f"gmm rho=alpha*eta K=5/5: mask diff {diff}/{total}, state bad {bad}/{n}, not bit-equal {neq}")
     assert diff <= MASK_TOL * total and bad == 0
+
+
+@pytest.mark.parametrize("Kc,Kd,rho_mode,decision,mode", [
+    (3, 3, 0, 0, "device"), (5, 5, 1, 0, "host"), (7, 3, 0, 1, "device"), (1, 1, 0, 0, "strided")])
+def test_gmm_parity_per_channel_variances(Kc, Kd, rho_mode, decision, mode):
+    # one variance per colour channel (v_init and v_min split evenly over the channels):
+    # bit-exact model state; masks exact except for the density decision's exp (MASK_TOL)
+    cfg = preset("gmm_320x240", H=45, W=131, n_objects=3, illumination=True, camouflage=True)
+    p = GmmParams(Kc=Kc, Kd=Kd, rho_mode=rho_mode, decision=decision, var_mode=1)
+    diff, total, n, bad, neq = _run_gmm_pair(cfg, p, 40, host_frames=mode == "host",
+                                             strided=mode == "strided")
+    log(f"gmm per-channel variances K={Kc}/{Kd} rho_mode={rho_mode} decision={decision} {mode}: "
+        f"mask diff {diff}/{total}, state bad {bad}/{n}, not bit-equal {neq}")
+    assert bad == 0 and neq == 0
+    assert diff == 0 if decision == 0 else diff <= MASK_TOL * total
+
+
+def test_gmm_per_channel_state_round_trip():
+    # the exported blob carries the per-channel flag; restoring it into a model with the
+    # same parameters continues bit for bit, and so does the oracle from the unpacked planes
+    from paper_2002_00250_amd import fgs
+    cfg = preset("gmm_320x240", H=33, W=71, n_objects=2)
+    p = GmmParams(Kc=7, Kd=3, var_mode=1)
+    sc = Scene(cfg)
+    frames = [sc.frame(t)[:2] for t in range(24)]
+    a = _model(fgs.FGS_GMM, cfg.H, cfg.W, p)
+    for rgb, D in frames[:12]:
+        a.push(*to_dev(rgb, D))
+    blob = a.state_blob()
+    st = fgs.unpack_state(blob)
+    assert st["v_c"].shape == (7, 3, cfg.H, cfg.W)
+    np.testing.assert_array_equal(fgs.pack_state(st), blob)
+    b = _model(fgs.FGS_GMM, cfg.H, cfg.W, p)
+    b.set_state(blob)
+    with pytest.raises(fgs.FgsError) as e:          # isotropic model: layout mismatch
+        _model(fgs.FGS_GMM, cfg.H, cfg.W, GmmParams(Kc=7, Kd=3)).set_state(blob)
+    assert e.value.status == fgs.FGS_ERR_INVALID_ARG
+    ref = GmmRef(cfg.H, cfg.W, p)
+    ref.set_state_planes(st)
+    for rgb, D in frames[12:]:
+        a.push(*to_dev(rgb, D))
+        b.push(*to_dev(rgb, D))
+        exp = ref.step(rgb, D)
+        np.testing.assert_array_equal(a.mask_host(), b.mask_host())
+        np.testing.assert_array_equal(a.mask_host(), exp)
+    np.testing.assert_array_equal(a.state_blob(), b.state_blob())
+    n, bad, neq = compare_gmm_state(a.state(), ref.state_planes())
+    assert bad == 0 and neq == 0
+    a.close()
+    b.close()
 
 
 def test_gmm_legacy_params_struct_means_rho_alpha():
