@@ -237,12 +237,13 @@ fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset);
 /*
  * Model state, serialised in a fixed layout (little-endian):
  *   header (64 bytes): uint32 magic 0x53534746 ("FGSS"), uint32 version (1),
- *     uint32 algo, int32 H, int32 W, int32 A, int32 B, int32 reserved,
+ *     uint32 algo, int32 H, int32 W, int32 A, int32 B, int32 flags,
  *     int64 frames pushed, uint64 seed (PBAS, else 0), 16 bytes reserved.
- *     A,B = Kc,Kd (GMM) or N,0 (PBAS).
+ *     A,B = Kc,Kd (GMM) or N,0 (PBAS).  flags bit 0: GMM per-channel colour
+ *     variances (var_mode 1); every other bit zero.
  *   GMM payload (float32 planes of H*W, row-major), in order:
- *     w_c[Kc], mu_c[Kc][3] (R,G,B), v_c[Kc], w_d[Kd], mu_d[Kd], v_d[Kd]
- *     (each model's Gaussians in rank order).
+ *     w_c[Kc], mu_c[Kc][3] (R,G,B), v_c[Kc] (v_c[Kc][3] with flags bit 0),
+ *     w_d[Kd], mu_d[Kd], v_d[Kd] (each model's Gaussians in rank order).
  *   PBAS payload: samples[N] uint32 planes (bytes R,G,B,depth code),
  *     dhist[N] uint32 planes (bytes D_R, D_G, D_B, D_D), R[4] float32 planes,
  *     T[4] float32 planes, S[4] uint16 planes.
@@ -251,7 +252,8 @@ fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset);
  * last frame), then copies; FGS_MEM_HOST waits for completion.  fgs_set_state
  * replaces the model (including the frame counter, which keys the PBAS random
  * stream) from such a blob for the same algo/H/W/A/B.
- * Errors: INVALID_ARG (size or header mismatch), DEVICE.
+ * A device buffer (FGS_MEM_DEVICE) must be 4-byte aligned.
+ * Errors: INVALID_ARG (size or header mismatch, misaligned device buffer), DEVICE.
  */
 fgs_status fgs_state_size(const fgs_model* m, size_t* bytes);
 fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where);

@@ -78,7 +78,9 @@ hipError_t gmm_window_launch_forward(const GmmWindowArgs& a, int K, hipStream_t 
 hipError_t gmm_window_launch_backward(const GmmWindowArgs& a, int K, hipStream_t s);
 
 // --------------------------------------------------------------- PBAS ----
-// Device layout: samples[N] and dhist[N] uint32 planes (bytes R,G,B,depth), R and
+// Device layout: samples in ceil(N/4) planes of 16-byte quads (slot k of pixel p
+// = word k & 3 of quad (k >> 2) * npix + p; padding slots zero), dhist[N] uint32
+// planes (a sample and a D word hold bytes R,G,B,depth), R and
 // T as one float4 per pixel, S as four uint16 per pixel (uint2), `last` = the
 // pixel's previous RGBD8 word, and two ping-pong planes of neighbour-update fire
 // bits (one byte per pixel, bit j: channel j wrote into a neighbour at that frame;

@@ -38,30 +38,43 @@ constexpr int kHaloH = kTileH + 2;
 __device__ __forceinline__ int nb_dx(int d) { return (d == 0 || d == 3 || d == 5) ? -1 : ((d == 1 || d == 6) ? 0 : 1); }
 __device__ __forceinline__ int nb_dy(int d) { return d < 3 ? -1 : (d < 5 ? 0 : 1); }
 
+// D history: slot k of pixel p is the 32-bit word k * npix + p (one byte per channel).
 __device__ __forceinline__ uint8_t* byte_at(uint32_t* plane0, int64_t npix, int slot, int p, int j) {
     return reinterpret_cast<uint8_t*>(plane0 + (int64_t)slot * npix + p) + j;
 }
 
-// Sample planes are touched once per frame: non-temporal when the device's
-// resident model state exceeds the last-level cache (see gmm_kernels.hip).  A slot
-// is read and written through a raw buffer resource over its plane (base uniform
-// across the wavefront, range = one plane, so the hardware drops any access
-// outside it) with the pixel's 32-bit byte offset: no per-slot address is held in
-// vector registers.
+// Sample storage: slot k of pixel p is word k & 3 of the 16-byte element
+// (k >> 2) * npix + p of the sample array ("quad planes" of four slots), so a
+// wavefront moves 1 KiB contiguous per load or store instruction.  Slots from N
+// up to the next multiple of 4 are padding and stay zero.
+__device__ __forceinline__ uint8_t* sample_byte(uint32_t* samples, int64_t npix, int slot, int p, int j) {
+    return reinterpret_cast<uint8_t*>(samples + (((int64_t)(slot >> 2) * npix + p) << 2) + (slot & 3)) + j;
+}
+
+// Sample quads are touched once per frame: non-temporal when the device's
+// resident model state exceeds the last-level cache (see gmm_kernels.hip).  A quad
+// plane is read and written through a raw buffer resource whose base is the
+// tile's first pixel in that plane (uniform across the wavefront) with the
+// lane's 32-bit byte offset from there, so no per-quad address is held in vector
+// registers; the range ends at the plane's end, and the hardware drops any
+// access beyond it.
 constexpr int kBufferWord3 = 0x00020000;  // raw 32-bit buffer, gfx9 family
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const uint32_t* plane0, uint32_t plane_bytes,
-                                                            int k) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(plane0) + (size_t)k * (plane_bytes >> 2),
-                                             (short)0, (int)plane_bytes, kBufferWord3);
+typedef uint32_t u32x4 __attribute__((__vector_size__(4 * sizeof(uint32_t))));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t quad_rsrc(const uint32_t* tile0, int64_t npix, uint32_t range,
+                                                           int q) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(tile0) + (size_t)q * (size_t)npix * 4u,
+                                             (short)0, (int)range, kBufferWord3);
 }
 template <bool NT>
-__device__ __forceinline__ uint32_t ld_slot(const uint32_t* plane0, uint32_t plane_bytes, int k, uint32_t boff) {
-    return __builtin_amdgcn_raw_buffer_load_b32(plane_rsrc(plane0, plane_bytes, k), boff, 0, NT ? 2 : 0);
+__device__ __forceinline__ u32x4 ld_quad(const uint32_t* tile0, int64_t npix, uint32_t range, int q, uint32_t voff) {
+    return __builtin_amdgcn_raw_buffer_load_b128(quad_rsrc(tile0, npix, range, q), voff, 0, NT ? 2 : 0);
 }
 template <bool NT>
-__device__ __forceinline__ void st_slot(uint32_t* plane0, uint32_t plane_bytes, int k, uint32_t boff, uint32_t v) {
-    __builtin_amdgcn_raw_buffer_store_b32(v, plane_rsrc(plane0, plane_bytes, k), boff, 0, NT ? 2 : 0);
+__device__ __forceinline__ void st_quad(uint32_t* tile0, int64_t npix, uint32_t range, int q, uint32_t voff,
+                                        u32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(v, quad_rsrc(tile0, npix, range, q), voff, 0, NT ? 2 : 0);
 }
 
 // Where channel j of pixel q sends its neighbour write at frame t: direction and
@@ -203,11 +216,25 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 #pragma unroll
     for (int j = 0; j < 4; ++j) dold[j] = cand[j] ? (int)*byte_at(a.m.dhist, npix, ks[j], p, j) : 0;
 
+    // Quads 4q < N hold samples (the first NLO slots need no run-time test);
+    // padding slots come in as zero and are never used.
     uint32_t sm[NMAX];
-    const uint32_t boff = (uint32_t)p * 4u;
-    const uint32_t pbytes = (uint32_t)npix * 4u;  // npix <= 2^28
+    const int64_t p0 = (int64_t)y0 * W + x0;                     // tile origin, < npix
+    const uint32_t* stile = a.m.samples + p0 * 4;
+    const int64_t qleft = (npix - p0) * 16;                       // bytes from the origin to the plane end
+    const uint32_t qrange = qleft > 0xFFFFFFFFll ? 0xFFFFFFFFu : (uint32_t)qleft;
+    const uint32_t voff = (uint32_t)(p - p0) * 16u;               // p - p0 < npix <= 2^28
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k) sm[k] = (k < NLO || k < N) ? ld_slot<NT>(a.m.samples, pbytes, k, boff) : 0u;
+    for (int q = 0; q < NMAX / 4; ++q) {
+        if (4 * q < NLO || 4 * q < N) {
+            const u32x4 v = ld_quad<NT>(stile, npix, qrange, q, voff);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sm[4 * q + i] = v[i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sm[4 * q + i] = 0u;
+        }
+    }
 
     // Classification: an integer distance d is within R iff d < min(ceil(R), 256)
     // (no d is within a threshold R <= 0 or NaN).
@@ -320,14 +347,17 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         T[j] = fminf(fmaxf(tt, a.c.T_lower), a.c.T_upper);
     }
 
-    // The store loop rebuilds each plane's descriptor (a few scalar instructions)
-    // rather than keeping N of them alive across the frame; the empty asm hides
-    // that the base is the one the loads used.
-    uint32_t* sbase = a.m.samples;
+    // The store loop rebuilds each quad plane's descriptor (a few scalar
+    // instructions) rather than keeping them alive across the frame; the empty asm
+    // hides that the base is the one the loads used.
+    uint32_t* sbase = a.m.samples + p0 * 4;
     asm volatile("" : "+s"(sbase));
 #pragma unroll
-    for (int k = 0; k < NMAX; ++k)
-        if (k < NLO || k < N) st_slot<NT>(sbase, pbytes, k, boff, sm[k]);
+    for (int q = 0; q < NMAX / 4; ++q)
+        if (4 * q < NLO || 4 * q < N) {
+            const u32x4 v = {sm[4 * q], sm[4 * q + 1], sm[4 * q + 2], sm[4 * q + 3]};
+            st_quad<NT>(sbase, npix, qrange, q, voff, v);
+        }
     // R, T and S are written only where they changed (bit for bit): on a static
     // background R and T sit at their lower bounds and S moves only with D.
     {
@@ -349,7 +379,7 @@ __device__ __forceinline__ void fill_pixel(const PbasStepArgs& a, int p) {
     const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
     const uint32_t Iw = (uint32_t)px[0] | ((uint32_t)px[1] << 8) | ((uint32_t)px[2] << 16) |
                         (depth_code(dmm, a.c.depth_max_mm) << 24);
-    a.m.samples[(int64_t)a.t * a.npix + p] = Iw;
+    *reinterpret_cast<uint32_t*>(sample_byte(a.m.samples, a.npix, (int)a.t, p, 0)) = Iw;
     a.m.last[p] = Iw;
     a.m.mask[p] = 0;
 }

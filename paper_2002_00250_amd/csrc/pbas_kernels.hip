@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void pbas_flush_kernel(PbasPlanes m, int H, in
             intent_of(w1.v[j], N, dq, slot);
             const uint32_t val = (lastw >> (8 * j)) & 0xFFu;
             if (dq != 7 - d || (j == 3 && val == 0u)) continue;
-            *byte_at(m.samples, npix, slot, p, j) = (uint8_t)val;
+            *sample_byte(m.samples, npix, slot, p, j) = (uint8_t)val;
         }
     }
 }
@@ -88,6 +88,30 @@ __global__ void pbas_import_rts_kernel(PbasPlanes m, int npix, const float* rt, 
     m.T[p] = make_float4(rt[4 * n + p], rt[5 * n + p], rt[6 * n + p], rt[7 * n + p]);
     m.S[p] = make_uint2((uint32_t)s[0 * n + p] | ((uint32_t)s[1 * n + p] << 16),
                         (uint32_t)s[2 * n + p] | ((uint32_t)s[3 * n + p] << 16));
+}
+
+// Canonical slot-major sample planes (plane k = slot k of every pixel) <-> the
+// device's quad planes.  Import writes the padding slots as zero.
+__global__ void pbas_export_samples_kernel(const uint4* quads, uint32_t* out, int npix, int N) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const int64_t n = npix;
+    for (int q = 0; 4 * q < N; ++q) {
+        const uint4 v = quads[q * n + p];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+        for (int i = 0; i < 4 && 4 * q + i < N; ++i) out[(4 * q + i) * n + p] = w[i];
+    }
+}
+
+__global__ void pbas_import_samples_kernel(uint4* quads, const uint32_t* in, int npix, int N) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const int64_t n = npix;
+    for (int q = 0; 4 * q < N; ++q) {
+        uint32_t w[4];
+        for (int i = 0; i < 4; ++i) w[i] = 4 * q + i < N ? in[(4 * q + i) * n + p] : 0u;
+        quads[q * n + p] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
 }
 
 inline unsigned blocks1d(int n) { return (unsigned)((n + 255) / 256); }
@@ -144,10 +168,13 @@ hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev,
     return hipGetLastError();
 }
 
-// Canonical payload: samples[N] u32, dhist[N] u32, R[4] f32, T[4] f32, S[4] u16.
+// Canonical payload: samples[N] u32, dhist[N] u32, R[4] f32, T[4] f32, S[4] u16
+// (out and in are 4-byte aligned device buffers).
 hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out, hipStream_t s) {
     const size_t plane = (size_t)npix * 4;
-    hipError_t e = hipMemcpyAsync(out, m.samples, plane * N, hipMemcpyDeviceToDevice, s);
+    hipLaunchKernelGGL(pbas_export_samples_kernel, dim3(blocks1d(npix)), dim3(256), 0, s,
+                       reinterpret_cast<const uint4*>(m.samples), reinterpret_cast<uint32_t*>(out), npix, N);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(out + plane * N, m.dhist, plane * N, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
@@ -160,7 +187,9 @@ hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out
 hipError_t pbas_launch_import(const PbasPlanes& m, int npix, int N, const uint8_t* in,
                               hipStream_t s) {
     const size_t plane = (size_t)npix * 4;
-    hipError_t e = hipMemcpyAsync(m.samples, in, plane * N, hipMemcpyDeviceToDevice, s);
+    hipLaunchKernelGGL(pbas_import_samples_kernel, dim3(blocks1d(npix)), dim3(256), 0, s,
+                       reinterpret_cast<uint4*>(m.samples), reinterpret_cast<const uint32_t*>(in), npix, N);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(m.dhist, in + plane * N, plane * N, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;

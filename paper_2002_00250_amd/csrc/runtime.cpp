@@ -373,7 +373,7 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         off += align256((size_t)gmm_planes(m->gp.Kc, m->gp.Kd, m->gp.var_mode) * n * 16);
     } else {
         const size_t N = (size_t)m->pp.N;
-        o_samples = off; off += align256(N * n * 4);
+        o_samples = off; off += align256((size_t)((N + 3) & ~3) * n * 4);  // quad planes
         o_dhist = off;   off += align256(N * n * 4);
         o_R = off;       off += align256(n * 16);
         o_T = off;       off += align256(n * 16);
@@ -623,6 +623,8 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
         return fail(FGS_ERR_INVALID_ARG, "state buffer is %zu bytes, need %zu", bytes, kHeaderBytes + payload);
     if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
         return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    if (where == FGS_MEM_DEVICE && ((uintptr_t)dst & 3))
+        return fail(FGS_ERR_INVALID_ARG, "device state buffer must be 4-byte aligned");
     fgs_status st = flush_pending(m);
     if (st != FGS_OK) return st;
 
@@ -672,6 +674,8 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
         return fail(FGS_ERR_INVALID_ARG, "state blob is %zu bytes, need %zu", bytes, kHeaderBytes + payload);
     if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
         return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    if (where == FGS_MEM_DEVICE && ((uintptr_t)src & 3))
+        return fail(FGS_ERR_INVALID_ARG, "device state blob must be 4-byte aligned");
     StateHeader h;
     if (where == FGS_MEM_HOST) {
         std::memcpy(&h, src, sizeof h);

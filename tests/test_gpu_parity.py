@@ -444,6 +444,17 @@ def test_error_paths():
     assert m.t == 1 and not m.mask_host().any()
     with pytest.raises(fgs.FgsError):
         m.set_state(np.zeros(10, np.uint8))
+    # device state buffers must be 4-byte aligned (checked before any device work)
+    size = len(m.state_blob())
+    buf = torch.zeros(size + 8, dtype=torch.uint8, device="cuda")
+    for call in (lambda: fgs.fgs_copy_state(m.handle, buf.data_ptr() + 2, size, fgs.FGS_MEM_DEVICE),
+                 lambda: fgs.fgs_set_state(m.handle, buf.data_ptr() + 1, size, fgs.FGS_MEM_DEVICE)):
+        with pytest.raises(fgs.FgsError) as e:
+            call()
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG
+    fgs.fgs_copy_state(m.handle, buf.data_ptr() + 4, size, fgs.FGS_MEM_DEVICE)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(buf[4:4 + size].cpu().numpy(), m.state_blob())
     p = fgs.fgs_gmm_params_default()
     p.Kc, p.Kd = 4, 2
     with pytest.raises(fgs.FgsError):
