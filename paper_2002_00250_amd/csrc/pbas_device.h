@@ -120,18 +120,41 @@ struct PbasLds {
 // and slot, and each write that lands inside the tile sets its (slot, channel) bit
 // in the destination's bit-words with an LDS atomic OR.  Whether the destination
 // had depth at t-1 is checked by the destination.
-template <int NMAX>
-__device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint8_t* fire, int x0, int y0,
-                                                int H, int W, int N, uint32_t t_prev, uint32_t k0,
-                                                uint32_t k1) {
-    for (int i = threadIdx.x; i < kHaloW * kHaloH; i += kBlock) {
+//
+// Lane tid reads halo pixels tid and tid + kBlock (row-major over the
+// (kTileW + 2) x (kTileH + 2) halo); the bytes are loaded first and scattered
+// later, so the loads overlap the tile's other reads.
+static_assert(kHaloW * kHaloH <= 2 * kBlock, "two halo pixels per lane");
+
+struct FireIn {
+    uint32_t fb[2];  // fire byte (0: nothing to scatter, or no such pixel)
+    int q[2];        // its pixel index
+};
+
+__device__ __forceinline__ FireIn load_fire(const uint8_t* fire, int x0, int y0, int H, int W) {
+    FireIn f;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int i = (int)threadIdx.x + r * kBlock;
         const int hx = i % kHaloW, hy = i / kHaloW;
         const int gx = x0 + hx - 1, gy = y0 + hy - 1;
-        if (gx < 0 || gx >= W || gy < 0 || gy >= H) continue;
-        const int q = gy * W + gx;
-        const uint32_t fb = fire[q];
+        f.fb[r] = 0u;
+        f.q[r] = gy * W + gx;
+        if (i < kHaloW * kHaloH && gx >= 0 && gx < W && gy >= 0 && gy < H) f.fb[r] = fire[f.q[r]];
+    }
+    return f;
+}
+
+template <int NMAX>
+__device__ __forceinline__ void scatter_fired(PbasLds<NMAX>& sh, const FireIn& f, int N, uint32_t t_prev,
+                                              uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const uint32_t fb = f.fb[r];
         if (fb == 0u) continue;
-        const U32x4 w1 = philox4x32_10((uint32_t)q, t_prev, 1u, 0u, k0, k1);
+        const int i = (int)threadIdx.x + r * kBlock;
+        const int hx = i % kHaloW, hy = i / kHaloW;
+        const U32x4 w1 = philox4x32_10((uint32_t)f.q[r], t_prev, 1u, 0u, k0, k1);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (!((fb >> j) & 1u)) continue;
@@ -152,10 +175,12 @@ __device__ __forceinline__ void scatter_intents(PbasLds<NMAX>& sh, const uint8_t
 // The pixel's N sample words live in registers between one dense coalesced read
 // and one dense coalesced write of the sample planes: frame t-1's neighbour
 // writes and this frame's self-update are merged in registers with per-slot byte
-// masks, so no sample plane sees a partial-line write.  The Philox draws and the
-// 1/T tests do not depend on the classification, so the candidate self-update
-// slots are known first and their D-history bytes are fetched before the
-// samples, off the critical path.
+// masks, so no sample plane sees a partial-line write.  Every read of the frame
+// is issued before the scatter of the neighbour writes (fire bytes first, then
+// the pixel's state and samples), and since the Philox draws and the 1/T tests
+// do not depend on the classification, the candidate self-update slots are known
+// early and their D-history bytes are fetched during the scatter, off the critical
+// path.
 //
 // Classification runs two channels per 32-bit word (16-bit lanes: R|B and G|D).
 // The depth lane holds code - 1, so an empty depth slot (code 0) becomes 0xFFFF,
@@ -167,54 +192,35 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     const int tid = threadIdx.x;
     const int lx = tid % kTileW, ly = tid / kTileW;
     const int x0 = bx * kTileW, y0 = by * kTileH;
-    const int x = x0 + lx, y = y0 + ly;
     const int W = a.W, H = a.H;
     const int64_t npix = a.npix;
     const int N = a.c.N;
+    // Every lane issues its reads before the scatter so that their latency overlaps
+    // it; a lane past the image edge reads the tile origin's pixel (always inside)
+    // and leaves after the scatter without writing anything.
+    const bool inside = x0 + lx < W && y0 + ly < H;
+    const int x = inside ? x0 + lx : x0, y = inside ? y0 + ly : y0;
+    const int p = y * W + x;
 
+    FireIn fin = {{0u, 0u}, {0, 0}};
     if (a.apply_pending) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) sh.pend[w * kBlock + tid] = 0u;
-        __syncthreads();
-        scatter_intents<NMAX>(sh, a.m.fire[(a.t - 1u) & 1u], x0, y0, H, W, N, a.t - 1u, a.c.key0, a.c.key1);
-        __syncthreads();
+        fin = load_fire(a.m.fire[(a.t - 1u) & 1u], x0, y0, H, W);
     }
-    if (x >= W || y >= H) return;
-    const int p = y * W + x;
 
-    // Ingest.
-    const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
-    const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
-    const bool valid = dmm > 0u;
-    const uint32_t I0 = px[0], I1 = px[1], I2 = px[2];
-    const uint32_t I3 = depth_code(dmm, a.c.depth_max_mm);
-    const uint32_t Iw = I0 | (I1 << 8) | (I2 << 16) | (I3 << 24);
-
-    const float4 Rv = a.m.R[p];
+    // The pixel's own reads: T first (the self-update draws need it), then R, S, the
+    // previous value and the frame.  The scheduling fences keep them ahead of the
+    // sample reads: loads complete in order, so the D-history reads that wait for T
+    // then need not wait for the samples.
     const float4 Tv = a.m.T[p];
+    const float4 Rv = a.m.R[p];
     const uint2 Sv = a.m.S[p];
     const uint32_t lastw = a.m.last[p];
-    float R[4] = {Rv.x, Rv.y, Rv.z, Rv.w};
-    float T[4] = {Tv.x, Tv.y, Tv.z, Tv.w};
-    int S[4] = {(int)(Sv.x & 0xFFFFu), (int)(Sv.x >> 16), (int)(Sv.y & 0xFFFFu), (int)(Sv.y >> 16)};
-    const bool active[4] = {true, true, true, valid};
-
-    // Block 0 of the Philox draws drives the self-update.
-    const U32x4 w0 = philox4x32_10((uint32_t)p, a.t, 0u, 0u, a.c.key0, a.c.key1);
-    const float inv16 = 1.0f / 65536.0f;
-
-    // Self-update candidates: the 1/T test with T from before this frame.
-    bool cand[4];
-    int ks[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t a0 = w0.v[j];
-        cand[j] = active[j] && (float)(a0 >> 16) * inv16 * T[j] < 1.0f;
-        ks[j] = (int)(__umul24(a0 & 0xFFFFu, (uint32_t)N) >> 16);  // 16 x 7 bits: 24-bit multiply
-    }
-    int dold[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) dold[j] = cand[j] ? (int)*byte_at(a.m.dhist, npix, ks[j], p, j) : 0;
+    const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
+    const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
+    const uint32_t I0 = px[0], I1 = px[1], I2 = px[2];
+    __builtin_amdgcn_sched_barrier(0);
 
     // Quads 4q < N hold samples (the first NLO slots need no run-time test);
     // padding slots come in as zero and are never used.
@@ -235,6 +241,42 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             for (int i = 0; i < 4; ++i) sm[4 * q + i] = 0u;
         }
     }
+
+    __builtin_amdgcn_sched_barrier(0);
+
+    // Ingest (the depth code needs the depth read; computed once every read is issued).
+    const bool valid = dmm > 0u;
+    const uint32_t I3 = depth_code(dmm, a.c.depth_max_mm);
+    const uint32_t Iw = I0 | (I1 << 8) | (I2 << 16) | (I3 << 24);
+    float R[4] = {Rv.x, Rv.y, Rv.z, Rv.w};
+    float T[4] = {Tv.x, Tv.y, Tv.z, Tv.w};
+    int S[4] = {(int)(Sv.x & 0xFFFFu), (int)(Sv.x >> 16), (int)(Sv.y & 0xFFFFu), (int)(Sv.y >> 16)};
+    const bool active[4] = {true, true, true, valid};
+
+    // Block 0 of the Philox draws drives the self-update.
+    const U32x4 w0 = philox4x32_10((uint32_t)p, a.t, 0u, 0u, a.c.key0, a.c.key1);
+    const float inv16 = 1.0f / 65536.0f;
+
+    if (a.apply_pending) {
+        __syncthreads();  // bit-words cleared
+        scatter_fired<NMAX>(sh, fin, N, a.t - 1u, a.c.key0, a.c.key1);
+    }
+
+    // Self-update candidates: the 1/T test with T from before this frame.
+    bool cand[4];
+    int ks[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t a0 = w0.v[j];
+        cand[j] = active[j] && (float)(a0 >> 16) * inv16 * T[j] < 1.0f;
+        ks[j] = (int)(__umul24(a0 & 0xFFFFu, (uint32_t)N) >> 16);  // 16 x 7 bits: 24-bit multiply
+    }
+    int dold[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dold[j] = cand[j] ? (int)*byte_at(a.m.dhist, npix, ks[j], p, j) : 0;
+
+    if (a.apply_pending) __syncthreads();  // every write aimed at the tile recorded
+    if (!inside) return;
 
     // Classification: an integer distance d is within R iff d < min(ceil(R), 256)
     // (no d is within a threshold R <= 0 or NaN).
