@@ -80,10 +80,18 @@ class PbasParams:
     seed: int = PBAS_DEFAULT_SEED
 
 
-def pbas_draws(H: int, W: int, t: int, seed: int):
-    """Philox words for frame t: (w0, w1), each uint32 [H, W, 4] (word j -> channel j)."""
+def pbas_draws(H: int, W: int, t: int, seed: int, origin=None):
+    """Philox words for frame t: (w0, w1), each uint32 [H, W, 4] (word j -> channel j).
+    The counter's first word is the pixel's linear index y * W_img + x in the whole image;
+    ``origin = (y0, x0, W_img)`` places this H x W array as a window of a larger image."""
     k0, k1 = seed_key(seed)
-    pix = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    if origin is None:
+        pix = np.arange(H * W, dtype=np.uint64).reshape(H, W)
+    else:
+        y0, x0, W_img = origin
+        ys = np.arange(y0, y0 + H, dtype=np.uint64)[:, None]
+        xs = np.arange(x0, x0 + W, dtype=np.uint64)[None, :]
+        pix = ys * np.uint64(W_img) + xs
     out = []
     for c in (0, 1):
         x = philox4x32_10(pix, np.uint64(t), np.uint64(c), np.uint64(0), k0, k1)
@@ -94,9 +102,15 @@ def pbas_draws(H: int, W: int, t: int, seed: int):
 class PbasRef:
     """The RGB-D PBAS over an H x W image.  ``step(rgb, depth) -> mask``."""
 
-    def __init__(self, H: int, W: int, params: PbasParams | None = None):
+    def __init__(self, H: int, W: int, params: PbasParams | None = None, origin=None):
+        """``origin = (y0, x0, W_img)``: this model is the window of rows y0.. and columns
+        x0.. of a W_img-wide image, and draws that image's random numbers.  Writes that the
+        image's pixels outside the window would send into it are not modelled, so only the
+        window's outermost ring can differ from the whole image's model, and only in its
+        samples."""
         self.p = params or PbasParams()
         self.H, self.W = H, W
+        self.origin = origin
         N = self.p.N
         self.samples = np.zeros((N, H, W, 4), np.uint8)
         self.D = np.zeros((N, H, W, 4), np.uint8)
@@ -143,7 +157,7 @@ class PbasRef:
         mask = np.where(F.any(axis=-1), 255, 0).astype(np.uint8)
         bg = active & ~F
 
-        w0, w1 = pbas_draws(H, W, self.t, p.seed)
+        w0, w1 = pbas_draws(H, W, self.t, p.seed, self.origin)
         self.last_draws = (w0, w1)
         scale = np.float32(1.0 / 65536.0)
         T_prev = self.T

@@ -21,10 +21,14 @@ __global__ __launch_bounds__(256) void pbas_fill_kernel(PbasStepArgs a) {
 // Register capacity class NMAX serves N in [class_min(NMAX), NMAX].
 constexpr int class_min(int nmax) { return nmax <= 8 ? 2 : (nmax <= 40 ? nmax - 3 : nmax - 7); }
 
+// One block per 64x4 tile on a one-dimensional grid (row-major tile order): the
+// grid's y extent is too small for the tile rows of a tall image.
 template <int NMAX, bool NT>
 __global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
     __shared__ PbasLds<NMAX> sh;
-    pbas_tile<NMAX, class_min(NMAX), NT>(a, blockIdx.x, blockIdx.y, sh);
+    const int tiles_x = (a.W + kTileW - 1) / kTileW;
+    const int b = (int)blockIdx.x;
+    pbas_tile<NMAX, class_min(NMAX), NT>(a, b % tiles_x, b / tiles_x, sh);
 }
 
 // Apply the neighbour writes of the last processed frame (read-out of the logical
@@ -155,8 +159,9 @@ hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
     if ((int)a.t < a.c.N) {
         hipLaunchKernelGGL(pbas_fill_kernel, dim3(blocks1d(a.npix)), dim3(256), 0, s, a);
     } else {
-        const dim3 grid((a.W + kTileW - 1) / kTileW, (a.H + kTileH - 1) / kTileH);
-        launch_step_n(a, grid, s);
+        // ceil(W/64) * ceil(H/4) <= H*W/256 + W/64 + H/4 + 1 < 2^27 tiles for H*W <= 2^28
+        const int64_t tiles = (int64_t)((a.W + kTileW - 1) / kTileW) * ((a.H + kTileH - 1) / kTileH);
+        launch_step_n(a, dim3((unsigned)tiles), s);
     }
     return hipGetLastError();
 }

@@ -140,6 +140,37 @@ def test_neighbour_writes_gathered_independently():
         np.testing.assert_array_equal(ref.samples, expect, err_msg=f"frame {t}")
 
 
+def test_window_model_matches_whole_image_except_ring_samples():
+    # A window of a larger image drawn with the image's pixel indices: from the same state,
+    # one frame gives the whole image's mask, R, T, S and D on the window, and its samples
+    # everywhere but the window's outermost ring (writes from outside are not modelled).
+    cfg = preset("pbas_640x480", H=14, W=18, n_objects=2)
+    p = PbasParams(N=6, T_lower=1.0, T_upper=4.0, seed=9)
+    sc = Scene(cfg)
+    full = PbasRef(14, 18, p)
+    y0, x0, h, w = 3, 4, 7, 9
+    ring_diff = 0
+    w0f, w1f = pbas_draws(14, 18, 11, p.seed)
+    w0w, w1w = pbas_draws(h, w, 11, p.seed, (y0, x0, 18))
+    np.testing.assert_array_equal(w0w, w0f[y0:y0 + h, x0:x0 + w])
+    np.testing.assert_array_equal(w1w, w1f[y0:y0 + h, x0:x0 + w])
+    for t in range(24):
+        rgb, D, _ = sc.frame(t)
+        win = PbasRef(h, w, p, origin=(y0, x0, 18))
+        st = full.state_planes()
+        win.set_state_planes({k: (v[..., y0:y0 + h, x0:x0 + w] if k != "t" else v) for k, v in st.items()})
+        m_win = win.step(rgb[y0:y0 + h, x0:x0 + w], D[y0:y0 + h, x0:x0 + w])
+        m_full = full.step(rgb, D)
+        np.testing.assert_array_equal(m_win, m_full[y0:y0 + h, x0:x0 + w])
+        a, b = win.state_planes(), full.state_planes()
+        for k in ("dhist", "R", "T", "S"):
+            np.testing.assert_array_equal(a[k], b[k][..., y0:y0 + h, x0:x0 + w], err_msg=f"{k} t={t}")
+        sa, sb = a["samples"], b["samples"][:, y0:y0 + h, x0:x0 + w]
+        np.testing.assert_array_equal(sa[:, 1:-1, 1:-1], sb[:, 1:-1, 1:-1], err_msg=f"t={t}")
+        ring_diff += int((sa != sb).sum())
+    assert ring_diff > 0          # writes from outside the window do reach its ring
+
+
 def test_update_rate_and_uniform_choices():
     # Fixed T: the self-update fires with probability 1/T; slots and directions uniform.
     cfg = preset("pbas_640x480", H=64, W=64, n_objects=0, illumination=False, camouflage=False)
