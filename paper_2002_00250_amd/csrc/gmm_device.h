@@ -314,24 +314,31 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     const int y = p / a.W;
     const int x = p - y * a.W;
 
+    // Every read is issued before any result is used (the frame first, then the
+    // state planes): loads complete in order, and the depth code's branch would
+    // otherwise wait for the frame before the state reads go out.
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
     const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
-    const float Xc[3] = {(float)px[0], (float)px[1], (float)px[2]};
-    const bool valid = dmm > 0u;
-    const float Xd[1] = {(float)depth_code(dmm, a.c.depth_max_mm)};
-
+    const uint32_t r0 = px[0], r1 = px[1], r2 = px[2];
     const float4* st = a.state;
     float4 core[KC];
-    float ex[4 * E];
+    float4 exv[E];
 #pragma unroll
     for (int k = 0; k < KC; ++k) core[k] = ld_state<NT>(st + (int64_t)k * a.npix + p);
 #pragma unroll
+    for (int e = 0; e < E; ++e) exv[e] = ld_state<NT>(st + (int64_t)(KC + e) * a.npix + p);
+    __builtin_amdgcn_sched_barrier(0);
+
+    const float Xc[3] = {(float)r0, (float)r1, (float)r2};
+    const bool valid = dmm > 0u;
+    const float Xd[1] = {(float)depth_code(dmm, a.c.depth_max_mm)};
+    float ex[4 * E];
+#pragma unroll
     for (int e = 0; e < E; ++e) {
-        const float4 f = ld_state<NT>(st + (int64_t)(KC + e) * a.npix + p);
-        ex[4 * e + 0] = f.x;
-        ex[4 * e + 1] = f.y;
-        ex[4 * e + 2] = f.z;
-        ex[4 * e + 3] = f.w;
+        ex[4 * e + 0] = exv[e].x;
+        ex[4 * e + 1] = exv[e].y;
+        ex[4 * e + 2] = exv[e].z;
+        ex[4 * e + 3] = exv[e].w;
     }
     Mix<KC, 3, CV> mc;
     Mix<KD, 1> md;

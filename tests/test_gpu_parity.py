@@ -447,6 +447,7 @@ def test_error_paths():
     # device state buffers must be 4-byte aligned (checked before any device work)
     size = len(m.state_blob())
     buf = torch.zeros(size + 8, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()      # the fill runs on torch's stream, the copy on the model's
     for call in (lambda: fgs.fgs_copy_state(m.handle, buf.data_ptr() + 2, size, fgs.FGS_MEM_DEVICE),
                  lambda: fgs.fgs_set_state(m.handle, buf.data_ptr() + 1, size, fgs.FGS_MEM_DEVICE)):
         with pytest.raises(fgs.FgsError) as e:
