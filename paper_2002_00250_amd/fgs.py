@@ -387,7 +387,12 @@ def pack_state(st: dict) -> np.ndarray:
 class Model:
     """A background model on the current GPU.  Frames are torch tensors (device or host)
     or numpy arrays; ``rgb`` [H, W, 3] uint8, ``depth`` [H, W] uint16 (torch: int16 view
-    or uint16)."""
+    or uint16).
+
+    The model runs on its own stream (or the one given).  Device tensors are ordered with
+    torch's current stream: the model's stream waits for the work queued there before it
+    reads a tensor passed in, and torch's current stream waits for the model before it
+    uses a tensor the model wrote."""
 
     def __init__(self, algo: int, H: int, W: int, params=None, stream=None):
         import torch
@@ -397,6 +402,18 @@ class Model:
         handle = stream.cuda_stream if stream is not None else 0
         self.handle = fgs_create(algo, H, W, params, handle)
         self._mask_ptr = fgs_mask_device_ptr(self.handle)
+        self._ext = None
+
+    def _model_stream(self):
+        if self._ext is None:
+            self._ext = self._torch.cuda.ExternalStream(fgs_stream(self.handle))
+        return self._ext
+
+    def _model_waits_for_torch(self):
+        self._model_stream().wait_stream(self._torch.cuda.current_stream())
+
+    def _torch_waits_for_model(self):
+        self._torch.cuda.current_stream().wait_stream(self._model_stream())
 
     def close(self):
         if getattr(self, "handle", None):
@@ -427,6 +444,8 @@ class Model:
         rs = rgb.stride(0) if not isinstance(rgb, np.ndarray) else rgb.strides[0]
         ds = (depth.stride(0) * 2) if not isinstance(depth, np.ndarray) else depth.strides[0]
         dh, dw = int(depth.shape[0]), int(depth.shape[1])
+        if wr == FGS_MEM_DEVICE:
+            self._model_waits_for_torch()
         if (dh, dw) == (self.H, self.W):
             fgs_push_frame(self.handle, pr, rs, pd, ds, wr)
         else:
@@ -444,6 +463,7 @@ class Model:
             g = np.ascontiguousarray(gt, np.uint8)
             fgs_eval_accumulate(self.handle, g.ctypes.data, g.strides[0], FGS_MEM_HOST)
         else:
+            self._model_waits_for_torch()
             fgs_eval_accumulate(self.handle, gt.data_ptr(), gt.stride(0), FGS_MEM_DEVICE)
 
     def eval_read(self, reset: bool = False) -> tuple:
@@ -452,7 +472,9 @@ class Model:
 
     def mask_into(self, out) -> None:
         """Device-to-device copy of the latest mask into a uint8 [H, W] cuda tensor."""
+        self._model_waits_for_torch()
         fgs_get_mask(self.handle, out.data_ptr(), out.stride(0), FGS_MEM_DEVICE)
+        self._torch_waits_for_model()
 
     def state_blob(self) -> np.ndarray:
         n = fgs_state_size(self.handle)

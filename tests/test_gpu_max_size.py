@@ -63,6 +63,7 @@ def _device_blob(m):
     from paper_2002_00250_amd import fgs
     n = fgs.fgs_state_size(m.handle)
     blob = torch.empty(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()          # the memory may still be in use on torch's stream
     fgs.fgs_copy_state(m.handle, blob.data_ptr(), n, fgs.FGS_MEM_DEVICE)
     torch.cuda.synchronize()
     return blob

@@ -96,6 +96,7 @@ def _run_gmm_pair(cfg, p, frames, host_frames=False, strided=False):
             r, d = to_dev(rgb, D)
             pad_r[:, :3 * cfg.W] = r.reshape(cfg.H, -1)
             pad_d[:, :cfg.W] = d
+            torch.cuda.synchronize()      # filled on torch's stream, read on the model's
             fgs.fgs_push_frame(m.handle, pad_r.data_ptr(), pad_r.stride(0), pad_d.data_ptr(),
                                pad_d.stride(0) * 2, fgs.FGS_MEM_DEVICE)
             torch.cuda.synchronize()
@@ -217,6 +218,28 @@ def test_gmm_per_channel_state_round_trip():
     assert bad == 0 and neq == 0
     a.close()
     b.close()
+
+
+def test_model_orders_device_tensors_with_torch_stream():
+    # frames uploaded asynchronously on torch's stream and pushed at once, masks written into
+    # a tensor and read back on torch's stream at once: the binding orders the two streams
+    from paper_2002_00250_amd import fgs
+    cfg = preset("gmm_320x240", n_objects=3)
+    p = GmmParams(Kc=3, Kd=3)
+    sc = Scene(cfg)
+    ref = GmmRef(cfg.H, cfg.W, p)
+    m = _model(fgs.FGS_GMM, cfg.H, cfg.W, p)
+    out = torch.empty((cfg.H, cfg.W), dtype=torch.uint8, device="cuda")
+    for t in range(25):
+        rgb, D, _ = sc.frame(t)
+        r = torch.from_numpy(rgb).pin_memory().cuda(non_blocking=True)
+        d = torch.from_numpy(D.view(np.int16)).pin_memory().cuda(non_blocking=True)
+        m.push(r, d)
+        m.mask_into(out)
+        got = out.cpu().numpy()
+        np.testing.assert_array_equal(got, ref.step(rgb, D), err_msg=f"frame {t}")
+        out.fill_(7)                       # torch overwrites it before the next mask lands
+    m.close()
 
 
 def test_gmm_legacy_params_struct_means_rho_alpha():
