@@ -390,9 +390,9 @@ class Model:
     or uint16).
 
     The model runs on its own stream (or the one given).  Device tensors are ordered with
-    torch's current stream: the model's stream waits for the work queued there before it
-    reads a tensor passed in, and torch's current stream waits for the model before it
-    uses a tensor the model wrote."""
+    torch's current stream: the model's stream waits for the work queued there before a
+    call that reads or writes a tensor, and torch's current stream then waits for the
+    model, so a tensor the model wrote is ready and one it read may be reused or freed."""
 
     def __init__(self, algo: int, H: int, W: int, params=None, stream=None):
         import torch
@@ -417,6 +417,7 @@ class Model:
 
     def close(self):
         if getattr(self, "handle", None):
+            self._ext = None              # wraps the model's stream, destroyed next
             fgs_destroy(self.handle)
             self.handle = None
 
@@ -450,6 +451,10 @@ class Model:
             fgs_push_frame(self.handle, pr, rs, pd, ds, wr)
         else:
             fgs_push_frame_scaled(self.handle, pr, rs, pd, ds, dh, dw, wr)
+        if wr == FGS_MEM_DEVICE:
+            # torch's stream may reuse the frames' memory only after the model has read them
+            # (no record_stream: the model's stream can be destroyed before the tensors are)
+            self._torch_waits_for_model()
 
     def mask_host(self) -> np.ndarray:
         out = np.empty((self.H, self.W), np.uint8)
@@ -465,6 +470,7 @@ class Model:
         else:
             self._model_waits_for_torch()
             fgs_eval_accumulate(self.handle, gt.data_ptr(), gt.stride(0), FGS_MEM_DEVICE)
+            self._torch_waits_for_model()
 
     def eval_read(self, reset: bool = False) -> tuple:
         """(TP, TN, FP, FN) accumulated since creation or the last reset."""
