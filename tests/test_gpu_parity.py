@@ -275,7 +275,7 @@ def test_gmm_parity_1280x720_k5_sampled_pixels():
     ref = GmmRef(1, sel.size, p)
     m = _model(fgs.FGS_GMM, cfg.H, cfg.W, p)
     diff = total = 0
-    frames = 120
+    frames = 200
     for t in range(frames):
         rgb, D, _ = sc.frame(t)
         r, d = to_dev(rgb, D)
@@ -410,13 +410,13 @@ def test_pbas_parity_1280x720_n35_transitions():
     sc = Scene(cfg)
     ref = PbasRef(cfg.H, cfg.W, p)
     m = _model(fgs.FGS_PBAS, cfg.H, cfg.W, p)
-    for t in range(80):
+    for t in range(200):
         rgb, D, _ = sc.frame(t)
-        if t in (35, 36, 79):
+        if t in (35, 36, 79, 199):
             ref.set_state_planes(m.state())
             exp = ref.step(rgb, D)
         m.push(*to_dev(rgb, D))
-        if t in (35, 36, 79):
+        if t in (35, 36, 79, 199):
             got = m.mask_host()
             res = compare_pbas_state(m.state(), ref.state_planes())
             log(f"pbas 1280x720 N=35 transition at t={t}: mask diff {int((got != exp).sum())}, state {res}")
