@@ -416,6 +416,9 @@ fgs_status fgs_server_submit(fgs_server* s, int32_t id, const uint8_t* rgb, cons
     std::memcpy(sl.h_in, rgb, (size_t)st->npix * 3);
     std::memcpy(sl.h_in + st->rgb_bytes, depth, (size_t)st->npix * 2);
     lk.lock();
+    // A close that ran during the copy marked the slot dropped (its host buffers stay
+    // until destroy): the ticket stays valid and its wait reports the drop.
+    if (sl.state != kFilling) return FGS_OK;
     sl.state = kQueued;
     s->cv_sched.notify_one();
     return FGS_OK;

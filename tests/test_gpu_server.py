@@ -136,6 +136,47 @@ def test_backpressure_and_close_with_frames_queued():
     srv.destroy()
 
 
+def test_close_during_submit_never_strands_a_ticket():
+    # close_stream racing a submit whose frame copy is under way: the ticket must end as
+    # done or dropped (never left queued on a closed stream, where a wait would not return)
+    import threading
+    import time
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    H, W = 720, 1280
+    rgb = np.zeros((H, W, 3), np.uint8)
+    dep = np.full((H, W), 1500, np.uint16)
+    outcomes = {"done": 0, "dropped": 0, "refused": 0}
+    for rnd in range(4):
+        srv = Server(8 << 30, 4)
+        for i in range(30):
+            sid = srv.open(fgs.FGS_GMM, H, W, _params(fgs.FGS_GMM))
+            box = {}
+
+            def sub():
+                try:
+                    box["t"] = srv.submit(sid, rgb, dep)
+                except fgs.FgsError as err:
+                    box["err"] = err.status
+            th = threading.Thread(target=sub)
+            th.start()
+            time.sleep(1e-4 * (i % 8))
+            srv.close_stream(sid)
+            th.join()
+            if "t" in box:
+                try:
+                    srv.wait(box["t"], timeout_ms=5000)
+                    outcomes["done"] += 1
+                except fgs.FgsError as err:
+                    assert err.status == fgs.FGS_ERR_BAD_STATE, err.status   # BUSY: stranded
+                    outcomes["dropped"] += 1
+            else:
+                assert box["err"] == fgs.FGS_ERR_INVALID_ARG
+                outcomes["refused"] += 1
+        srv.destroy()
+    log(f"close during submit: {outcomes}")
+
+
 def test_32_streams_30fps_mixed_resolution():
     # 12x 424x240, 12x 640x480, 8x 1280x720; even streams GMM K=5, odd PBAS N=20;
     # frames at 30 fps, random phase, +-5 ms jitter.  p99 latency below one frame period,
