@@ -112,7 +112,7 @@ struct PbasStepArgs {
     int32_t H, W, npix;
     int32_t depth_h, depth_w;  // 0: depth is H x W; else its size, upscaled to H x W
     uint32_t t;            // frame index
-    int32_t apply_pending; // intents of frame t-1 still to be applied
+    int32_t apply_pending; // neighbour writes of frame t-1 (fire bytes) still to be applied
     int32_t streaming;     // 1: non-temporal sample traffic (working set beyond the last-level cache)
     PbasConsts c;
 };

@@ -34,7 +34,7 @@ struct fgs_model {
     hipEvent_t gt_done;
     bool gt_busy;
     int64_t t;          // frames pushed
-    bool pending;       // PBAS: intents of frame t-1 not yet applied
+    bool pending;       // PBAS: neighbour writes of frame t-1 not yet applied
     bool poisoned;
     int32_t cache_policy;  // fgs_cache_policy
 };
@@ -51,7 +51,7 @@ GmmConsts gmm_consts(const fgs_gmm_params& p);
 // Non-temporal state traffic for this model's next launch (cache policy).
 bool model_use_streaming(const fgs_model* m);
 // Launch arguments of the model's next frame read from device frames; advances the
-// model's frame counter and pending-intent flag exactly as a push does.
+// model's frame counter and pending-write flag exactly as a push does.
 // depth_h = depth_w = 0: the depth map has the model's size.
 void model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
                     int64_t depth_stride, int32_t depth_h, int32_t depth_w, GmmStepArgs* a);

@@ -173,9 +173,9 @@ __device__ __forceinline__ void scatter_fired(PbasLds<NMAX>& sh, const FireIn& f
 // N lies in [NLO, NMAX]: slots below NLO need no run-time bound check.
 //
 // The pixel's N sample words live in registers between one dense coalesced read
-// and one dense coalesced write of the sample planes: frame t-1's neighbour
+// and one dense coalesced write of the sample quad planes: frame t-1's neighbour
 // writes and this frame's self-update are merged in registers with per-slot byte
-// masks, so no sample plane sees a partial-line write.  Every read of the frame
+// masks, so no sample quad plane sees a partial-line write.  Every read of the frame
 // is issued before the scatter of the neighbour writes (fire bytes first, then
 // the pixel's state and samples), and since the Philox draws and the 1/T tests
 // do not depend on the classification, the candidate self-update slots are known
