@@ -259,6 +259,39 @@ fgs_status fgs_state_size(const fgs_model* m, size_t* bytes);
 fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where);
 fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem where);
 
+/*
+ * In-place access to the model's device state (Sec. 3.1, 3.2: the per-pixel model
+ * the host allocated on the device, Sec. 4.2), for callers that read it where it
+ * lives instead of copying it.  Each field is one per-pixel value: element p (the
+ * pixel y*W + x) of field f is at (const char*)f.base + p * f.pixel_stride, of type
+ * f.dtype.  Fields come in the serialised payload's order:
+ *   GMM:  w_c[k], mu_c[k][c], v_c[k] (v_c[k][c] with var_mode 1), w_d[k], mu_d[k],
+ *         v_d[k]; float32.
+ *   PBAS: samples[k] and dhist[k] uint32 (bytes R,G,B,depth), R[j], T[j] float32,
+ *         S[j] uint16.
+ * `name` is a static string naming the array, `index` the rank, slot or channel,
+ * `sub` the colour channel of mu_c and per-channel v_c (else 0).
+ * With fields == NULL (capacity ignored) the call only writes the number of fields
+ * to *count.  Otherwise capacity must be at least that number; a PBAS model first
+ * applies the neighbour writes still deferred from its last frame, on its stream,
+ * so that the fields hold the logical state after the last frame once the stream
+ * has reached this call (fgs_sync, or a wait on fgs_stream's stream).
+ * The addresses are borrowed: they stay valid until fgs_destroy; the next push or
+ * fgs_set_state changes what they hold.  Writing through them is not supported.
+ * Errors: INVALID_ARG (NULL count, capacity too small), DEVICE.
+ */
+typedef enum fgs_dtype { FGS_DTYPE_F32 = 1, FGS_DTYPE_U32 = 2, FGS_DTYPE_U16 = 3 } fgs_dtype;
+typedef struct fgs_state_field {
+    const char* name;
+    int32_t index;
+    int32_t sub;
+    int32_t dtype;        /* fgs_dtype */
+    int32_t elem_bytes;
+    const void* base;     /* device address of pixel 0's element */
+    int64_t pixel_stride; /* bytes from one pixel's element to the next pixel's */
+} fgs_state_field;
+fgs_status fgs_get_state(fgs_model* m, fgs_state_field* fields, int32_t capacity, int32_t* count);
+
 /* Number of frames pushed so far (the next frame's index). */
 fgs_status fgs_frame_index(const fgs_model* m, int64_t* t);
 

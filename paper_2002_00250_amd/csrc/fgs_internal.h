@@ -21,6 +21,13 @@ __host__ __device__ inline int gmm_extra_planes(int Kc, int Kd, int var_mode) {
     return (Kc + 3 * Kd + (var_mode ? 2 * Kc : 0) + 3) / 4;
 }
 __host__ __device__ inline int gmm_planes(int Kc, int Kd, int var_mode) { return Kc + gmm_extra_planes(Kc, Kd, var_mode); }
+// Float index of a field among the extra planes (float i sits in plane Kc + i/4, lane i%4).
+__host__ __device__ constexpr int gmm_x_wc(int, int, int k) { return k; }
+__host__ __device__ constexpr int gmm_x_wd(int Kc, int, int k) { return Kc + k; }
+__host__ __device__ constexpr int gmm_x_mud(int Kc, int Kd, int k) { return Kc + Kd + 2 * k; }
+__host__ __device__ constexpr int gmm_x_vd(int Kc, int Kd, int k) { return Kc + Kd + 2 * k + 1; }
+__host__ __device__ constexpr int gmm_x_vg(int Kc, int Kd, int k) { return Kc + 3 * Kd + 2 * k; }
+__host__ __device__ constexpr int gmm_x_vb(int Kc, int Kd, int k) { return Kc + 3 * Kd + 2 * k + 1; }
 bool gmm_supported(int Kc, int Kd);
 
 struct GmmConsts {

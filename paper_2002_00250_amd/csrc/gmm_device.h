@@ -286,12 +286,12 @@ template <int KC, int KD, int CV = 1>
 struct GmmLayout {
     static constexpr int NX = KC + 3 * KD + (CV == 3 ? 2 * KC : 0);  // extra floats
     static constexpr int E = (NX + 3) / 4;                            // extra planes
-    static constexpr int w_c(int k) { return k; }
-    static constexpr int w_d(int k) { return KC + k; }
-    static constexpr int mu_d(int k) { return KC + KD + 2 * k; }
-    static constexpr int v_d(int k) { return KC + KD + 2 * k + 1; }
-    static constexpr int v_g(int k) { return KC + 3 * KD + 2 * k; }
-    static constexpr int v_b(int k) { return KC + 3 * KD + 2 * k + 1; }
+    static constexpr int w_c(int k) { return gmm_x_wc(KC, KD, k); }
+    static constexpr int w_d(int k) { return gmm_x_wd(KC, KD, k); }
+    static constexpr int mu_d(int k) { return gmm_x_mud(KC, KD, k); }
+    static constexpr int v_d(int k) { return gmm_x_vd(KC, KD, k); }
+    static constexpr int v_g(int k) { return gmm_x_vg(KC, KD, k); }
+    static constexpr int v_b(int k) { return gmm_x_vb(KC, KD, k); }
 };
 
 // Scaled Eq. (1) factor of the Gaussian attaining delta (decision 1), in the order

@@ -34,14 +34,13 @@ __global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
     if (p < a.npix) gmm_pixel<KC, KD, NT, GEN ? 2 : 0, GEN ? 2 : 0, CV>(a, p);
 }
 
-// Index of a float among the extra planes (the layout of gmm_device.h, for run-time
-// Kc, Kd): w_c[k], w_d[k], then (mu_d, v_d) pairs by rank, then (v_g, v_b) pairs.
-__device__ __forceinline__ int x_wc(int, int, int k) { return k; }
-__device__ __forceinline__ int x_wd(int Kc, int, int k) { return Kc + k; }
-__device__ __forceinline__ int x_mud(int Kc, int Kd, int k) { return Kc + Kd + 2 * k; }
-__device__ __forceinline__ int x_vd(int Kc, int Kd, int k) { return Kc + Kd + 2 * k + 1; }
-__device__ __forceinline__ int x_vg(int Kc, int Kd, int k) { return Kc + 3 * Kd + 2 * k; }
-__device__ __forceinline__ int x_vb(int Kc, int Kd, int k) { return Kc + 3 * Kd + 2 * k + 1; }
+// Run-time Kc, Kd indices of the extra-plane fields (fgs_internal.h).
+__device__ __forceinline__ int x_wc(int Kc, int Kd, int k) { return gmm_x_wc(Kc, Kd, k); }
+__device__ __forceinline__ int x_wd(int Kc, int Kd, int k) { return gmm_x_wd(Kc, Kd, k); }
+__device__ __forceinline__ int x_mud(int Kc, int Kd, int k) { return gmm_x_mud(Kc, Kd, k); }
+__device__ __forceinline__ int x_vd(int Kc, int Kd, int k) { return gmm_x_vd(Kc, Kd, k); }
+__device__ __forceinline__ int x_vg(int Kc, int Kd, int k) { return gmm_x_vg(Kc, Kd, k); }
+__device__ __forceinline__ int x_vb(int Kc, int Kd, int k) { return gmm_x_vb(Kc, Kd, k); }
 
 __device__ __forceinline__ float* f4(float4* s, int64_t i) { return reinterpret_cast<float*>(s + i); }
 __device__ __forceinline__ const float* f4(const float4* s, int64_t i) {

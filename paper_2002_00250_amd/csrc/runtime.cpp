@@ -4,6 +4,7 @@
 // per-pixel work is done by the kernels in gmm_kernels.hip / pbas_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -13,6 +14,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "fgs.h"
 #include "fgs_internal.h"
@@ -709,6 +711,57 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
     if (e != hipSuccess) return device_fail(m, e, "set_state");
     m->t = h.frames;
     m->pending = false;
+    return FGS_OK;
+}
+
+fgs_status fgs_get_state(fgs_model* m, fgs_state_field* fields, int32_t capacity, int32_t* count) {
+    if (!m || !count) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    std::vector<fgs_state_field> f;
+    auto add = [&](const char* name, int index, int sub, int dtype, int bytes, const uint8_t* base,
+                   int64_t stride) {
+        f.push_back(fgs_state_field{name, index, sub, dtype, bytes, base, stride});
+    };
+    const int64_t n = m->npix;
+    if (m->algo == FGS_GMM) {
+        const int Kc = m->gp.Kc, Kd = m->gp.Kd, var = m->gp.var_mode;
+        const uint8_t* st = reinterpret_cast<const uint8_t*>(m->gmm_state);
+        auto core = [&](int k, int lane) { return st + (int64_t)k * n * 16 + 4 * lane; };
+        auto extra = [&](int i) { return st + (int64_t)(Kc + i / 4) * n * 16 + 4 * (i % 4); };
+        for (int k = 0; k < Kc; ++k) add("w_c", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_wc(Kc, Kd, k)), 16);
+        for (int k = 0; k < Kc; ++k)
+            for (int c = 0; c < 3; ++c) add("mu_c", k, c, FGS_DTYPE_F32, 4, core(k, c), 16);
+        for (int k = 0; k < Kc; ++k) {
+            add("v_c", k, 0, FGS_DTYPE_F32, 4, core(k, 3), 16);
+            if (var) {
+                add("v_c", k, 1, FGS_DTYPE_F32, 4, extra(gmm_x_vg(Kc, Kd, k)), 16);
+                add("v_c", k, 2, FGS_DTYPE_F32, 4, extra(gmm_x_vb(Kc, Kd, k)), 16);
+            }
+        }
+        for (int k = 0; k < Kd; ++k) add("w_d", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_wd(Kc, Kd, k)), 16);
+        for (int k = 0; k < Kd; ++k) add("mu_d", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_mud(Kc, Kd, k)), 16);
+        for (int k = 0; k < Kd; ++k) add("v_d", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_vd(Kc, Kd, k)), 16);
+    } else {
+        const int N = m->pp.N;
+        const uint8_t* smp = reinterpret_cast<const uint8_t*>(m->pb.samples);
+        const uint8_t* dh = reinterpret_cast<const uint8_t*>(m->pb.dhist);
+        for (int k = 0; k < N; ++k)  // quad planes: slot k is word k & 3 of quad (k >> 2)
+            add("samples", k, 0, FGS_DTYPE_U32, 4, smp + (int64_t)(k >> 2) * n * 16 + 4 * (k & 3), 16);
+        for (int k = 0; k < N; ++k) add("dhist", k, 0, FGS_DTYPE_U32, 4, dh + (int64_t)k * n * 4, 4);
+        for (int j = 0; j < 4; ++j)
+            add("R", j, 0, FGS_DTYPE_F32, 4, reinterpret_cast<const uint8_t*>(m->pb.R) + 4 * j, 16);
+        for (int j = 0; j < 4; ++j)
+            add("T", j, 0, FGS_DTYPE_F32, 4, reinterpret_cast<const uint8_t*>(m->pb.T) + 4 * j, 16);
+        for (int j = 0; j < 4; ++j)
+            add("S", j, 0, FGS_DTYPE_U16, 2, reinterpret_cast<const uint8_t*>(m->pb.S) + 2 * j, 8);
+    }
+    const int32_t need = (int32_t)f.size();
+    *count = need;
+    if (!fields) return FGS_OK;
+    if (capacity < need) return fail(FGS_ERR_INVALID_ARG, "capacity %d < %d fields", capacity, need);
+    fgs_status s = flush_pending(m);
+    if (s != FGS_OK) return s;
+    std::copy(f.begin(), f.end(), fields);
     return FGS_OK;
 }
 

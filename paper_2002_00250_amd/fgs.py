@@ -66,6 +66,14 @@ class fgs_server_stats(ctypes.Structure):
                 ("device_bytes_used", c_uint64), ("device_budget", c_uint64)]
 
 
+FGS_DTYPE_F32, FGS_DTYPE_U32, FGS_DTYPE_U16 = 1, 2, 3
+
+
+class fgs_state_field(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("index", c_int32), ("sub", c_int32), ("dtype", c_int32),
+                ("elem_bytes", c_int32), ("base", c_void_p), ("pixel_stride", c_int64)]
+
+
 _lib = None
 
 
@@ -92,6 +100,7 @@ def _load():
         "fgs_eval_accumulate": (S, [c_void_p, c_void_p, c_int64, c_int32]),
         "fgs_eval_read": (S, [c_void_p, POINTER(c_uint64), c_int32]),
         "fgs_state_size": (S, [c_void_p, POINTER(c_size_t)]),
+        "fgs_get_state": (S, [c_void_p, POINTER(fgs_state_field), c_int32, POINTER(c_int32)]),
         "fgs_copy_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
         "fgs_set_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
         "fgs_frame_index": (S, [c_void_p, POINTER(c_int64)]),
@@ -207,6 +216,17 @@ def fgs_state_size(m: int) -> int:
     out = c_size_t()
     _check(_load().fgs_state_size(c_void_p(m), byref(out)))
     return out.value
+
+
+def fgs_get_state(m: int) -> list:
+    """The model's state fields in place: [{name, index, sub, dtype, elem_bytes, base,
+    pixel_stride}] (device addresses, borrowed; see include/fgs.h)."""
+    n = c_int32()
+    _check(_load().fgs_get_state(c_void_p(m), None, 0, byref(n)))
+    arr = (fgs_state_field * n.value)()
+    _check(_load().fgs_get_state(c_void_p(m), arr, n.value, byref(n)))
+    return [dict(name=f.name.decode(), index=f.index, sub=f.sub, dtype=f.dtype, elem_bytes=f.elem_bytes,
+                 base=f.base or 0, pixel_stride=f.pixel_stride) for f in arr]
 
 
 def fgs_copy_state(m: int, dst: int, nbytes: int, where: int) -> None:

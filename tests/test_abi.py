@@ -101,7 +101,8 @@ def test_errors_without_device(libfgs):
     for call in (lambda: fgs.fgs_eval_accumulate(0, 0, 16, fgs.FGS_MEM_HOST),
                  lambda: fgs.fgs_eval_read(0),
                  lambda: fgs.fgs_push_frame(0, 0, 0, 0, 0, fgs.FGS_MEM_HOST),
-                 lambda: fgs.fgs_get_mask(0, 0, 16, fgs.FGS_MEM_HOST)):
+                 lambda: fgs.fgs_get_mask(0, 0, 16, fgs.FGS_MEM_HOST),
+                 lambda: fgs.fgs_get_state(0)):
         with pytest.raises(fgs.FgsError) as e:
             call()
         assert e.value.status == fgs.FGS_ERR_INVALID_ARG
