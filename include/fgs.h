@@ -370,7 +370,8 @@ fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w);
  *   streams N <= pbas_N_max (<= 40).  Uses the current device.
  * fgs_server_open: admit a stream (params as in fgs_create).  BUSY when the
  *   budget or the stream slots would be exceeded (nothing is allocated then);
- *   UNSUPPORTED for a K or N outside the server's classes.
+ *   UNSUPPORTED for a K or N outside the server's classes, or for GMM per-channel
+ *   colour variances (var_mode 1); the rate and decision variants are served.
  * fgs_server_submit: copy one host frame (dense rgb uint8[H][W][3], depth
  *   uint16[H][W]) into the stream's ring (4 frames) and return a ticket; the
  *   buffers may be reused at once.  t_arrival_s is the frame's arrival on the

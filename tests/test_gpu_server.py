@@ -21,11 +21,13 @@ def _gpu():
     yield
 
 
-def _params(algo, K=5, N=20, seed=None):
+def _params(algo, K=5, N=20, seed=None, gmm_variant=False):
     from paper_2002_00250_amd import fgs
     if algo == fgs.FGS_GMM:
         p = fgs.fgs_gmm_params_default()
         p.Kc = p.Kd = K
+        if gmm_variant:                   # rate alpha / w and the density decision
+            p.rho_mode, p.decision = 1, 1
     else:
         p = fgs.fgs_pbas_params_default()
         p.N = N
@@ -50,7 +52,8 @@ def _alone(algo, H, W, params, frames):
     return out
 
 
-def test_mix_equals_alone():
+@pytest.mark.parametrize("gmm_variant", [False, True])
+def test_mix_equals_alone(gmm_variant):
     from paper_2002_00250_amd import fgs
     from paper_2002_00250_amd.serving import Server
     specs = [(fgs.FGS_GMM, 48, 64), (fgs.FGS_PBAS, 48, 64), (fgs.FGS_GMM, 70, 100),
@@ -60,7 +63,7 @@ def test_mix_equals_alone():
     srv = Server(1 << 30, 16, gmm_K=5, pbas_N_max=24)
     streams = []
     for i, (algo, H, W) in enumerate(specs):
-        p = _params(algo, seed=1000 + i)
+        p = _params(algo, seed=1000 + i, gmm_variant=gmm_variant)
         streams.append((srv.open(algo, H, W, p), algo, H, W, p, _frames(H, W, T, seed=50 + i)))
     got = {sid: [] for sid, *_ in streams}
     for t in range(T):
@@ -105,6 +108,11 @@ def test_admission_by_budget_and_close():
     ids[0] = srv.open(fgs.FGS_GMM, 240, 320, _params(fgs.FGS_GMM))   # admitted again
     with pytest.raises(fgs.FgsError) as e:
         srv.open(fgs.FGS_GMM, 24, 32, _params(fgs.FGS_GMM, K=3))     # wrong K class
+    assert e.value.status == fgs.FGS_ERR_UNSUPPORTED
+    pv = _params(fgs.FGS_GMM)
+    pv.var_mode = 1                                                 # per-channel variances
+    with pytest.raises(fgs.FgsError) as e:
+        srv.open(fgs.FGS_GMM, 24, 32, pv)
     assert e.value.status == fgs.FGS_ERR_UNSUPPORTED
     srv.destroy()
 
