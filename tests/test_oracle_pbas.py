@@ -171,6 +171,32 @@ def test_window_model_matches_whole_image_except_ring_samples():
     assert ring_diff > 0          # writes from outside the window do reach its ring
 
 
+def test_window_from_frame_zero_matches_inside_a_margin():
+    # Run alone from frame 0, a window differs from the whole image only through the writes
+    # its outside neighbours send in; after u updating frames every field agrees at least
+    # u pixels from the window's inner edges (and the ring does differ at some point).
+    cfg = preset("pbas_640x480", H=26, W=34, n_objects=2)
+    p = PbasParams(N=4, T_lower=1.0, T_upper=4.0, seed=21)
+    sc = Scene(cfg)
+    full = PbasRef(26, 34, p)
+    y0, x0, h, w = 4, 5, 18, 22
+    win = PbasRef(h, w, p, origin=(y0, x0, 34))
+    outer_diff = 0
+    for t in range(12):
+        rgb, D, _ = sc.frame(t)
+        mw = win.step(rgb[y0:y0 + h, x0:x0 + w], D[y0:y0 + h, x0:x0 + w])
+        mf = full.step(rgb, D)[y0:y0 + h, x0:x0 + w]
+        u = max(0, t - p.N + 1)
+        inner = (slice(u, h - u), slice(u, w - u))
+        a, b = win.state_planes(), full.state_planes()
+        np.testing.assert_array_equal(mw[inner], mf[inner], err_msg=f"mask t={t}")
+        for k in ("samples", "dhist", "R", "T", "S"):
+            bk = b[k][..., y0:y0 + h, x0:x0 + w]
+            np.testing.assert_array_equal(a[k][(Ellipsis,) + inner], bk[(Ellipsis,) + inner], err_msg=f"{k} t={t}")
+            outer_diff += int((a[k] != bk).sum())
+    assert outer_diff > 0
+
+
 def test_update_rate_and_uniform_choices():
     # Fixed T: the self-update fires with probability 1/T; slots and directions uniform.
     cfg = preset("pbas_640x480", H=64, W=64, n_objects=0, illumination=False, camouflage=False)
