@@ -187,7 +187,7 @@ def test_gmm_parity_per_channel_variances(Kc, Kd, rho_mode, decision, mode):
 
 def test_gmm_per_channel_state_round_trip():
     # the exported blob carries the per-channel flag; restoring it into a model with the
-    # same parameters continues bit for bit, and so does the oracle from the unpacked planes
+    # same parameters continues bit for bit, and both follow the oracle's own run
     from paper_2002_00250_amd import fgs
     cfg = preset("gmm_320x240", H=33, W=71, n_objects=2)
     p = GmmParams(Kc=7, Kd=3, var_mode=1)
@@ -205,8 +205,9 @@ def test_gmm_per_channel_state_round_trip():
     with pytest.raises(fgs.FgsError) as e:          # isotropic model: layout mismatch
         _model(fgs.FGS_GMM, cfg.H, cfg.W, GmmParams(Kc=7, Kd=3)).set_state(blob)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG
-    ref = GmmRef(cfg.H, cfg.W, p)
-    ref.set_state_planes(st)
+    ref = GmmRef(cfg.H, cfg.W, p)                   # from frame 0, on its own
+    for rgb, D in frames[:12]:
+        ref.step(rgb, D)
     for rgb, D in frames[12:]:
         a.push(*to_dev(rgb, D))
         b.push(*to_dev(rgb, D))
@@ -313,13 +314,12 @@ def test_gmm_state_round_trip_and_determinism():
         b.push(*to_dev(rgb, D))
         np.testing.assert_array_equal(a.mask_host(), b.mask_host())
     np.testing.assert_array_equal(a.state_blob(), b.state_blob())
-    # oracle continues from the same state
+    # the restored run ends where the oracle's own run from frame 0 ends
     ref = GmmRef(60, 90, p)
-    ref.set_state_planes(fgs.unpack_state(blob))
-    for rgb, D in frames[15:]:
+    for rgb, D in frames:
         ref.step(rgb, D)
-    n, bad, neq = compare_gmm_state(a.state(), ref.state_planes())
-    assert bad == 0
+    n, bad, neq = compare_gmm_state(b.state(), ref.state_planes())
+    assert bad == 0 and neq == 0
     a.close()
     b.close()
 
@@ -462,6 +462,11 @@ def test_pbas_state_round_trip_and_determinism():
         np.testing.assert_array_equal(ma, mc)   # reading the state does not perturb the run
     np.testing.assert_array_equal(a.state_blob(), b.state_blob())
     np.testing.assert_array_equal(a.state_blob(), c.state_blob())
+    ref = PbasRef(50, 70, p)                          # the oracle's own run from frame 0
+    for rgb, D in frames:
+        ref.step(rgb, D)
+    res = compare_pbas_state(b.state(), ref.state_planes())
+    assert all(v == 0 for v in res.values()), res
     for mdl in (a, b, c):
         mdl.close()
 
