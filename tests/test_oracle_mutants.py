@@ -1,0 +1,164 @@
+"""The oracle's pins catch plausible mistakes.  Each case plants one mistake in the oracle
+(a dropped term, a wrong sign, index, operand or order; the function's source rewritten
+in one place), then runs that model's pin tests: at least one must fail.  The mistakes
+live only in the test's patched copy; nothing here runs on the GPU."""
+import inspect
+import textwrap
+
+import numpy as np
+import pytest
+
+import oracle.depth
+import oracle.gmm
+import oracle.metrics
+import oracle.pbas
+import oracle.philox
+import test_oracle_depth
+import test_oracle_gmm
+import test_oracle_metrics
+import test_oracle_pbas
+import test_oracle_philox
+
+
+def _mutant(func, old, new):
+    """`func` with its source changed in one place, compiled in its module's namespace."""
+    src = textwrap.dedent(inspect.getsource(func))
+    assert src.count(old) == 1, (func.__qualname__, old)
+    ns = dict(inspect.getmodule(func).__dict__)
+    exec(compile(src.replace(old, new), f"<mutant of {func.__qualname__}>", "exec"), ns)
+    return ns[func.__name__]
+
+
+def _patch(monkeypatch, owner, name, new, test_modules):
+    """Replace owner.name, and every test module's own reference to the same object."""
+    orig = getattr(owner, name)
+    monkeypatch.setattr(owner, name, new)
+    for tm in test_modules:
+        for attr, val in list(vars(tm).items()):
+            if val is orig:
+                monkeypatch.setattr(tm, attr, new)
+
+
+def _pin_calls(mod):
+    """Every test function of a pin module with each of its parametrizations."""
+    calls = []
+    for name, fn in vars(mod).items():
+        if not name.startswith("test_") or not callable(fn):
+            continue
+        params = [m for m in getattr(fn, "pytestmark", []) if m.name == "parametrize"]
+        if not params:
+            if not inspect.signature(fn).parameters:
+                calls.append((name, fn, {}))
+            continue
+        argnames = [a.strip() for a in params[0].args[0].split(",")]
+        for vals in params[0].args[1]:
+            vals = vals if len(argnames) > 1 else (vals,)
+            calls.append((name, fn, dict(zip(argnames, vals))))
+    return calls
+
+
+def _caught(mod):
+    """Name of the first pin that fails (None if all pass)."""
+    for name, fn, kw in _pin_calls(mod):
+        try:
+            with np.errstate(all="ignore"):
+                fn(**kw)
+        except Exception:   # an assertion, or the planted mistake breaking the run
+            return name
+    return None
+
+
+GMM_MUTANTS = [
+    ("variance from the old mean", oracle.gmm, "update_mixture",
+     "            e = X[0] - mu_new[0]", "            e = X[0] - mix.mu[k, 0]"),
+    ("matched weight misses +alpha", oracle.gmm, "update_mixture",
+     "np.where(hit, a * mix.w[k] + alpha, a * mix.w[k])", "np.where(hit, a * mix.w[k], a * mix.w[k])"),
+    ("ranking ascending", oracle.gmm, "update_mixture",
+     "np.argsort(-key, axis=0", "np.argsort(key, axis=0"),
+    ("replacement mean into rank 0", oracle.gmm, "update_mixture",
+     "mu[K - 1] = np.where(rep[None], X, mu[K - 1])", "mu[0] = np.where(rep[None], X, mu[0])"),
+    ("no renormalisation", oracle.gmm, "update_mixture", "w = w / S[None]", "w = w"),
+    ("last channel dropped from d2", oracle.gmm, "sq_distances",
+     "for c in range(1, C):", "for c in range(1, max(1, C - 1)):"),
+    ("background count off by one", oracle.gmm, "background_count", "B[hit] = k + 1", "B[hit] = k"),
+    ("unused Gaussians may match", oracle.gmm, "first_match",
+     "(w[k] > 0) & (q[k] < lam2)", "(q[k] < lam2)"),
+    ("depth term subtracted", oracle.gmm.GmmRef, "step",
+     "Z = np.where(term_c, np.where(term_d, tc + td, tc), td)",
+     "Z = np.where(term_c, np.where(term_d, tc - td, tc), td)"),
+    ("lambda not squared", oracle.gmm.GmmRef, "step",
+     "lam2 = c[\"lam\"] * c[\"lam\"]", "lam2 = c[\"lam\"]"),
+    ("no variance floor", oracle.gmm, "update_mixture",
+     "v_new = np.maximum(v_new, v_min)", "v_new = v_new"),
+    ("last match instead of first", oracle.gmm, "first_match",
+     "for k in range(w.shape[0] - 1, -1, -1):", "for k in range(w.shape[0]):"),
+    ("depth term without valid depth", oracle.gmm.GmmRef, "step",
+     "term_d = valid & used_d", "term_d = used_d"),
+]
+
+PBAS_MUTANTS = [
+    ("R moves the wrong way", oracle.pbas.PbasRef, "step",
+     "self.R > dbar * f(p.R_scale)", "self.R < dbar * f(p.R_scale)"),
+    ("T increments swapped", oracle.pbas.PbasRef, "step",
+     "np.where(F, self.T + f(p.T_inc) / dbar, self.T - f(p.T_dec) / dbar)",
+     "np.where(F, self.T - f(p.T_dec) / dbar, self.T + f(p.T_inc) / dbar)"),
+    ("S misses the replaced D", oracle.pbas.PbasRef, "step",
+     "self.S[ys, xs, js] += dm - old", "self.S[ys, xs, js] += dm"),
+    ("neighbour gets the source's value", oracle.pbas.PbasRef, "step",
+     "self.samples[knb[ys, xs, js], ny, nx, js] = I[ny, nx, js]",
+     "self.samples[knb[ys, xs, js], ny, nx, js] = I[ys, xs, js]"),
+    ("empty depth slots counted", oracle.pbas.PbasRef, "step",
+     "filled[..., 3] = s[..., 3] != 0", "filled[..., 3] = True"),
+    ("distance equal to R matches", oracle.pbas.PbasRef, "step",
+     "cnt += filled & (dist < self.R)", "cnt += filled & (dist <= self.R)"),
+    ("one match too many needed", oracle.pbas.PbasRef, "step",
+     "F = active & (cnt < p.min_matches)", "F = active & (cnt <= p.min_matches)"),
+    ("neighbour offsets transposed", oracle.pbas.PbasRef, "step",
+     "ny, nx = ys + NB_DY[d], xs + NB_DX[d]", "ny, nx = ys + NB_DX[d], xs + NB_DY[d]"),
+    ("no R floor", oracle.pbas.PbasRef, "step",
+     "R_new = np.maximum(R_new, np.array(p.R_lower, f))", "R_new = R_new"),
+]
+
+OTHER_MUTANTS = [
+    ("depth code rounds down", oracle.depth, "depth_q8", "q = (255 * d + m // 2) // m", "q = (255 * d) // m",
+     test_oracle_depth),
+    ("upscale takes corners", oracle.depth, "upscale_nearest",
+     "ys = ((2 * np.arange(H, dtype=np.int64) + 1) * Hd) // (2 * H)",
+     "ys = (np.arange(H, dtype=np.int64) * Hd) // H", test_oracle_depth),
+    ("false positives and negatives swapped", oracle.metrics, "indicators",
+     "FNR=_div(fn, tp + fn)", "FNR=_div(fp, tp + fn)", test_oracle_metrics),
+]
+
+
+@pytest.mark.parametrize("what,owner,name,old,new", GMM_MUTANTS, ids=[m[0] for m in GMM_MUTANTS])
+def test_gmm_pins_catch(monkeypatch, what, owner, name, old, new):
+    _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [test_oracle_gmm])
+    assert _caught(test_oracle_gmm) is not None, what
+
+
+@pytest.mark.parametrize("what,owner,name,old,new", PBAS_MUTANTS, ids=[m[0] for m in PBAS_MUTANTS])
+def test_pbas_pins_catch(monkeypatch, what, owner, name, old, new):
+    _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [test_oracle_pbas])
+    assert _caught(test_oracle_pbas) is not None, what
+
+
+@pytest.mark.parametrize("what,owner,name,old,new,pins", OTHER_MUTANTS, ids=[m[0] for m in OTHER_MUTANTS])
+def test_other_pins_catch(monkeypatch, what, owner, name, old, new, pins):
+    _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [pins])
+    assert _caught(pins) is not None, what
+
+
+def test_philox_pin_catches_swapped_key_words(monkeypatch, rocrand_probe):
+    # a round that xors the key words into the wrong lanes: only the library comparison can
+    # see it (the two oracle implementations share nothing but the constants)
+    bad = _mutant(oracle.philox.philox4x32_10,
+                  "c = [hi1 ^ c[1] ^ np.uint64(ka), lo1, hi0 ^ c[3] ^ np.uint64(kb), lo0]",
+                  "c = [hi1 ^ c[1] ^ np.uint64(kb), lo1, hi0 ^ c[3] ^ np.uint64(ka), lo0]")
+    _patch(monkeypatch, oracle.philox, "philox4x32_10", bad, [test_oracle_philox])
+    with pytest.raises(AssertionError):
+        test_oracle_philox.test_matches_rocm_library(rocrand_probe)
+
+
+def test_unmutated_oracle_passes_its_pins():
+    for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics):
+        assert _caught(mod) is None, mod.__name__

@@ -36,6 +36,44 @@ def test_hand_derived_frames():
                 assert ref.T[0, 0].tolist() == fr["expect_T"]
 
 
+def test_hand_derived_boundaries():
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pbas_hand_boundaries.json")))
+    pr = dict(gold["params"])
+    pr["R_lower"] = tuple(pr["R_lower"])
+    for case in gold["cases"]:
+        for seed in (1, 7):
+            ref = PbasRef(1, 1, PbasParams(seed=seed, **pr))
+            for fr in case["fill"]:
+                ref.step(np.array(fr["rgb"], np.uint8).reshape(1, 1, 3), np.array([[fr["D"]]], np.uint16))
+            fr = case["frame"]
+            m = ref.step(np.array(fr["rgb"], np.uint8).reshape(1, 1, 3), np.array([[fr["D"]]], np.uint16))
+            assert m[0, 0] == case["mask"], case["note"]
+
+
+def test_rate_T_rises_for_foreground_and_falls_for_background():
+    # the update period T grows where a channel is foreground and shrinks where it is
+    # background (clamped to its bounds); channels not processed keep it
+    cfg = preset("pbas_640x480", H=48, W=64, n_objects=2)
+    p = PbasParams(N=8)
+    sc = Scene(cfg)
+    ref = PbasRef(48, 64, p)
+    up = down = 0
+    for t in range(40):
+        rgb, D, _ = sc.frame(t)
+        T0 = ref.T.copy()
+        ref.step(rgb, D)
+        if t < p.N:
+            continue
+        F = ref.last_F
+        active = np.ones_like(F)
+        active[..., 3] = D > 0
+        assert np.all(ref.T[F] >= T0[F]) and np.all(ref.T[active & ~F] <= T0[active & ~F])
+        np.testing.assert_array_equal(ref.T[~active], T0[~active])
+        up += int((ref.T[F] > T0[F]).sum())
+        down += int((ref.T[active & ~F] < T0[active & ~F]).sum())
+    assert up > 0 and down > 0
+
+
 def _run(cfg, params, frames, audit=None):
     sc = Scene(cfg)
     ref = PbasRef(cfg.H, cfg.W, params)

@@ -1,27 +1,12 @@
 """Pins for the oracle's Philox4x32-10 (Salmon et al., SC'11): the ROCm random-number
 library's implementation of the same bijection, compiled for the host, must give the
 same words; plus the two oracle implementations against each other and basic statistics."""
-import os
-import shutil
 import subprocess
 
 import numpy as np
 import pytest
 
 from oracle.philox import philox4x32_10, philox4x32_10_int
-
-HERE = os.path.dirname(os.path.abspath(__file__))
-HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-
-
-@pytest.fixture(scope="module")
-def rocrand_probe(tmp_path_factory):
-    if not os.path.exists(HIPCC) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
-        pytest.skip("ROCm random-number library headers not available")
-    exe = str(tmp_path_factory.mktemp("philox") / "rocrand_philox_host")
-    src = os.path.join(HERE, "helpers", "rocrand_philox_host.cpp")
-    subprocess.run([HIPCC, "-O1", "-o", exe, src], check=True, capture_output=True)
-    return exe
 
 
 def _cases(n, seed=11):
