@@ -41,6 +41,21 @@ def test_reverse_sweep_matches_central_differences(K, theta):
     assert abs(g[0]) > 0 and abs(g[1]) > 0 and abs(g[2]) > 0
 
 
+def test_reverse_sweep_through_the_variance_floor():
+    # a fast rate drives both variances onto their floors inside the window, so the clamped
+    # steps (whose variance no longer depends on theta) are part of what is differentiated
+    p = GmmParams(Kc=3, Kd=3)
+    theta = (0.15, 2.5, 1.0)
+    rgb, dep, gt = _frames(16, 20, 48)
+    Z, has, dc, dd = record_window(rgb, dep, p, theta)
+    assert dc.clamp.sum() >= 10 and dd.clamp.sum() >= 10
+    Z64 = replay_window(rgb, dep, p, dc, dd, theta, np.float64)
+    _, dZ = bce_loss_and_grad(Z64, has, gt)
+    g = reverse_gradient(rgb, dep, p, dc, dd, theta, dZ)
+    fd = fd_gradient(rgb, dep, gt, p, dc, dd, has, theta)
+    assert np.all(np.abs(g - fd) <= 1e-5 * np.abs(fd) + 1e-9), (g, fd)
+
+
 def test_no_depth_means_no_depth_weight_gradient():
     p = GmmParams(Kc=3, Kd=3)
     rgb, dep, gt = _frames(10, 12, 20)

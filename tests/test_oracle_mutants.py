@@ -8,11 +8,13 @@ import textwrap
 import numpy as np
 import pytest
 
+import oracle.adjoint
 import oracle.depth
 import oracle.gmm
 import oracle.metrics
 import oracle.pbas
 import oracle.philox
+import test_oracle_adjoint
 import test_oracle_depth
 import test_oracle_gmm
 import test_oracle_metrics
@@ -130,6 +132,18 @@ OTHER_MUTANTS = [
 ]
 
 
+ADJOINT_MUTANTS = [
+    ("lambda gradient ignores the depth weight", oracle.adjoint, "reverse_gradient",
+     "(on_c + wd * on_d)", "(on_c + on_d)"),
+    ("alpha gradient misses the variance path", oracle.adjoint, "_reverse_model",
+     "g_alpha += float(np.where(hit, av * (d2n - v[k]), 0.0).sum())", "g_alpha += 0.0"),
+    ("mean adjoint without the variance's pull", oracle.adjoint, "_reverse_model",
+     "a_mnew = a_mun[k] + av[None] * alpha * (-2.0) * (X - mnew)", "a_mnew = a_mun[k]"),
+    ("clamped variance passes its adjoint", oracle.adjoint, "_reverse_model",
+     "av = np.where(hit & ~dec.clamp[t], a_vn[k], 0.0)", "av = np.where(hit, a_vn[k], 0.0)"),
+]
+
+
 @pytest.mark.parametrize("what,owner,name,old,new", GMM_MUTANTS, ids=[m[0] for m in GMM_MUTANTS])
 def test_gmm_pins_catch(monkeypatch, what, owner, name, old, new):
     _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [test_oracle_gmm])
@@ -148,6 +162,12 @@ def test_other_pins_catch(monkeypatch, what, owner, name, old, new, pins):
     assert _caught(pins) is not None, what
 
 
+@pytest.mark.parametrize("what,owner,name,old,new", ADJOINT_MUTANTS, ids=[m[0] for m in ADJOINT_MUTANTS])
+def test_adjoint_pins_catch(monkeypatch, what, owner, name, old, new):
+    _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [test_oracle_adjoint])
+    assert _caught(test_oracle_adjoint) is not None, what
+
+
 def test_philox_pin_catches_swapped_key_words(monkeypatch, rocrand_probe):
     # a round that xors the key words into the wrong lanes: only the library comparison can
     # see it (the two oracle implementations share nothing but the constants)
@@ -160,5 +180,5 @@ def test_philox_pin_catches_swapped_key_words(monkeypatch, rocrand_probe):
 
 
 def test_unmutated_oracle_passes_its_pins():
-    for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics):
+    for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics, test_oracle_adjoint):
         assert _caught(mod) is None, mod.__name__
