@@ -113,6 +113,31 @@ def test_window_gradient_end_to_end_matches_fp64_reference(E):
     win.close()
 
 
+def test_window_gradient_through_the_variance_floor():
+    # a fast rate puts the variances on their floors inside the window: the clamped steps'
+    # adjoints must vanish on the GPU as in the fp64 reference
+    from paper_2002_00250_amd.adjoint import GmmWindow, GmmWindowFunction, window_bce_loss
+    p = GmmParams(Kc=3, Kd=3)
+    H, W, T = 40, 56, 48
+    rgb, dep, gt = Scene(preset("adjoint_640x480", H=H, W=W)).frames(0, T)
+    theta0 = (0.15, 2.5, 1.0)
+    loss_ref, dZ, g_ref, (has, dc, dd) = _oracle_grad(rgb, dep, gt, p, theta0)
+    assert dc.clamp.sum() >= 10 and dd.clamp.sum() >= 10
+    win = GmmWindow(T, H, W, _params_c(p), checkpoint_every=16)
+    theta = torch.tensor(theta0, dtype=torch.float32, device="cuda", requires_grad=True)
+    r, d, g = _dev(rgb, dep, gt)
+    Z, hasg = GmmWindowFunction.apply(theta, r, d, win)
+    loss = window_bce_loss(Z, hasg, g)
+    loss.backward()
+    gg = theta.grad.double().cpu().numpy()
+    rel = np.abs(gg - g_ref) / np.abs(g_ref)
+    log(f"adjoint alpha=0.15 ({int(dc.clamp.sum())} + {int(dd.clamp.sum())} clamped steps): grad gpu {gg} "
+        f"ref {g_ref} rel {rel}")
+    assert abs(loss.item() - loss_ref) <= 1e-4 * abs(loss_ref)
+    assert np.all(rel <= 1e-3)
+    win.close()
+
+
 def test_window_gradient_640x480_64_frames_sampled_pixels():
     # The 640x480, K=3, 64-frame, checkpoint-16 workload at full size.  Each pixel's
     # recursion is independent, so feeding dL/dZ on a sample of pixels (zero elsewhere)
