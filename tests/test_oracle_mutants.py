@@ -96,6 +96,18 @@ GMM_MUTANTS = [
      "for k in range(w.shape[0] - 1, -1, -1):", "for k in range(w.shape[0]):"),
     ("depth term without valid depth", oracle.gmm.GmmRef, "step",
      "term_d = valid & used_d", "term_d = used_d"),
+    ("rate alpha/w with the weight before its update", oracle.gmm, "update_mixture",
+     "rho = alpha / np.where(hit, w[k], f(1))", "rho = alpha / np.where(hit, mix.w[k], f(1))"),
+    ("rate alpha*eta without the 2 pi", oracle.gmm, "update_mixture",
+     "rho = alpha * (np.exp(f(-0.5) * q[k]) / (f(2.0 * np.pi) * vsum[k]))",
+     "rho = alpha * (np.exp(f(-0.5) * q[k]) / vsum[k])"),
+    ("density of the first background Gaussian", oracle.gmm.GmmRef, "step",
+     "vc = np.take_along_axis(variance_sum(self.colour.v), kc[None], axis=0)[0]",
+     "vc = variance_sum(self.colour.v)[0]"),
+    ("density decision inverted", oracle.gmm.GmmRef, "step",
+     "(P < f(self.p.density_threshold))", "(P > f(self.p.density_threshold))"),
+    ("per-channel variances not split", oracle.gmm.GmmRef, "step",
+     "(c[\"v_init_c\"] / f(3), c[\"v_min_c\"] / f(3)) if diag", "(c[\"v_init_c\"], c[\"v_min_c\"] / f(3)) if diag"),
 ]
 
 PBAS_MUTANTS = [
