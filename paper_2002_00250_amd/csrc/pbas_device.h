@@ -12,8 +12,8 @@
 // using its stored previous value, before it classifies.
 //
 // Tile shape: a 256-lane workgroup covers 64 columns x 4 rows, one wavefront per
-// row, one pixel per lane, so each sample-plane access of a wavefront is 256
-// contiguous bytes.
+// row, one pixel per lane, so each sample access of a wavefront (a 16-byte quad
+// of slots per lane) is 1 KiB of contiguous memory.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +24,6 @@
 
 namespace fgs {
 namespace pbas {
-
 
 constexpr int kTileW = 64;
 constexpr int kTileH = 4;
