@@ -183,7 +183,10 @@ fgs_status fgs_destroy(fgs_model* m);
  * FGS_MEM_DEVICE: the kernel reads the device buffers in stream order, and the
  * caller must not overwrite them before the step has run (fgs_sync or a later
  * stream event).  Asynchronous otherwise: the mask is ready in stream order.
- * Errors: INVALID_ARG, DEVICE.
+ * Errors: INVALID_ARG (NULL model or frame, a stride below the packed row, a
+ * depth pointer or stride that is not 2-byte aligned, a bad `where`), BAD_STATE
+ * (2^32 - 1 frames pushed: the PBAS random stream's frame counter is exhausted),
+ * DEVICE (the model is then poisoned: every later call but fgs_destroy fails).
  */
 fgs_status fgs_push_frame(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride,
                           const uint16_t* depth, int64_t depth_stride, fgs_mem where);
@@ -203,14 +206,16 @@ fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_s
 
 /*
  * Copy the mask of the most recent frame into `mask` (H rows of W bytes,
- * `stride` bytes apart).  FGS_MEM_HOST waits for the frame to finish;
- * FGS_MEM_DEVICE enqueues a device copy on the model's stream.
- * BAD_STATE before the first push.
+ * `stride` bytes apart; 255 = foreground, 0 = background).  FGS_MEM_HOST waits
+ * for the frame to finish; FGS_MEM_DEVICE enqueues a device copy on the model's
+ * stream.  Errors: INVALID_ARG (NULL, stride < W, bad `where`), BAD_STATE before
+ * the first push, DEVICE.
  */
 fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem where);
 
 /* Borrow the device pointer of the model's internal H*W mask buffer (valid
- * until fgs_destroy; rewritten by every push, in stream order). */
+ * until fgs_destroy; rewritten by every push, in stream order).  INVALID_ARG
+ * for NULL arguments. */
 fgs_status fgs_mask_device_ptr(fgs_model* m, const uint8_t** out);
 
 /*
@@ -231,7 +236,8 @@ fgs_status fgs_mask_device_ptr(fgs_model* m, const uint8_t** out);
 fgs_status fgs_eval_accumulate(fgs_model* m, const uint8_t* gt, int64_t gt_stride, fgs_mem where);
 
 /* Wait for the model's stream and write the accumulated counts to counts[0..3] =
- * TP, TN, FP, FN (host memory).  reset != 0 then clears the accumulator. */
+ * TP, TN, FP, FN (host memory; all zero if nothing was accumulated).  reset != 0
+ * then clears the accumulator.  INVALID_ARG for NULL arguments, DEVICE. */
 fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset);
 
 /*
@@ -292,16 +298,20 @@ typedef struct fgs_state_field {
 } fgs_state_field;
 fgs_status fgs_get_state(fgs_model* m, fgs_state_field* fields, int32_t capacity, int32_t* count);
 
-/* Number of frames pushed so far (the next frame's index). */
+/* Number of frames pushed so far (the next frame's index; it keys the PBAS
+ * random stream, Sec. 3.2).  INVALID_ARG for NULL arguments. */
 fgs_status fgs_frame_index(const fgs_model* m, int64_t* t);
 
-/* Block until all work queued on the model's stream has finished. */
+/* Block until all work queued on the model's stream has finished.  INVALID_ARG
+ * for NULL, DEVICE if that work failed. */
 fgs_status fgs_sync(fgs_model* m);
 
-/* The hipStream_t (as void*) the model runs on. */
+/* The hipStream_t (as void*) the model runs on (owned by the library unless the
+ * caller passed one to fgs_create).  INVALID_ARG for NULL arguments. */
 fgs_status fgs_stream(const fgs_model* m, void** hip_stream);
 
-/* Device bytes the model holds (state, scratch planes, mask, input staging). */
+/* Device bytes the model holds (state, scratch planes, mask, input staging).
+ * INVALID_ARG for NULL arguments. */
 fgs_status fgs_device_bytes(const fgs_model* m, size_t* bytes);
 
 /*
