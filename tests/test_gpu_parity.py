@@ -352,6 +352,11 @@ def _run_pbas_pair(cfg, p, frames, host_frames=False):
     (5, 3, 4, 30, "host"),
     (9, 130, 8, 40, "device"),
     (37, 64, 35, 70, "device"),
+    (21, 70, 41, 60, "device"),     # class 48: last quad not loaded (41 <= 44)
+    (21, 70, 47, 65, "host"),       # class 48: last quad loaded, one padding slot
+    (13, 67, 53, 70, "device"),     # class 56
+    (13, 67, 64, 80, "device"),     # class 64, the largest N
+    (6, 40, 3, 25, "device"),       # class 8 with one quad of padding
 ])
 def test_pbas_parity_trajectories(H, W, N, frames, mode):
     cfg = preset("pbas_640x480", H=H, W=W)
