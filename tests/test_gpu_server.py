@@ -92,6 +92,34 @@ def test_mix_equals_alone(gmm_variant):
     srv.destroy()
 
 
+def test_pbas_n_up_to_40_in_the_mix_equals_alone():
+    # the server's PBAS instance covers N <= 40 with run-time bounds on every quad of
+    # slots: N = 35 (one padding slot) and N = 5 next to each other in one launch
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    srv = Server(1 << 30, 8, gmm_K=3, pbas_N_max=40)
+    specs = [(fgs.FGS_PBAS, 70, 100, 35), (fgs.FGS_PBAS, 33, 47, 5), (fgs.FGS_GMM, 40, 64, 0)]
+    T = 45
+    streams = []
+    for i, (algo, H, W, N) in enumerate(specs):
+        p = _params(algo, K=3, N=max(N, 2), seed=77 + i)
+        streams.append((srv.open(algo, H, W, p), algo, H, W, p, _frames(H, W, T, seed=90 + i)))
+    got = {sid: [] for sid, *_ in streams}
+    for t in range(T):
+        tickets = [(sid, srv.submit(sid, *fr[t]), H, W) for sid, algo, H, W, p, fr in streams]
+        for sid, tk, H, W in tickets:
+            m = np.empty((H, W), np.uint8)
+            srv.wait(tk, m)
+            got[sid].append(m)
+    for sid, algo, H, W, p, fr in streams:
+        ref = _alone(algo, H, W, p, fr)
+        diff = sum(int((a != b).sum()) for a, b in zip(got[sid], ref))
+        log(f"server N<=40 mix: stream {sid} ({'GMM' if algo == fgs.FGS_GMM else 'PBAS N=%d' % p.N} {H}x{W}): "
+            f"{diff} mask pixels differ from alone")
+        assert diff == 0
+    srv.destroy()
+
+
 def test_admission_by_budget_and_close():
     from paper_2002_00250_amd import fgs
     from paper_2002_00250_amd.serving import Server
