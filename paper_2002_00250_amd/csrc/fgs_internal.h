@@ -109,6 +109,9 @@ struct PbasPlanes {
     uint32_t* last;
     uint8_t* fire[2];
     uint8_t* mask;
+    // 1: the previous value lives in sample slot N (the first padding slot of the last
+    // quad; set for N >= 33 not a multiple of 4) and `last` is unused; 0: in `last`.
+    int32_t last_in_pad;
 };
 
 struct PbasStepArgs {

@@ -212,10 +212,16 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     // previous value and the frame.  The scheduling fences keep them ahead of the
     // sample reads: loads complete in order, so the D-history reads that wait for T
     // then need not wait for the samples.
+    // The previous value sits in padding slot N when the model put it there (N >= 33,
+    // not a multiple of 4) and the class can select it from registers (at most 7
+    // candidate slots).  Smaller classes keep it in its plane: there the select would
+    // cost occupancy.
+    constexpr bool kPadOK = NMAX - NLO <= 7 && NMAX >= 36;
+    const bool in_pad = kPadOK && a.m.last_in_pad;
     const float4 Tv = a.m.T[p];
     const float4 Rv = a.m.R[p];
     const uint2 Sv = a.m.S[p];
-    const uint32_t lastw = a.m.last[p];
+    uint32_t lastw = in_pad ? 0u : a.m.last[p];
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
     const uint32_t dmm = load_depth(a.depth, a.depth_stride, x, y, a.W, a.H, a.depth_w, a.depth_h);
     const uint32_t I0 = px[0], I1 = px[1], I2 = px[2];
@@ -276,6 +282,12 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 
     if (a.apply_pending) __syncthreads();  // every write aimed at the tile recorded
     if (!inside) return;
+
+    if (in_pad) {
+#pragma unroll
+        for (int k = NLO; k < NMAX; ++k)
+            if (k == N) lastw = sm[k];
+    }
 
     // Classification: an integer distance d is within R iff d < min(ceil(R), 256)
     // (no d is within a threshold R <= 0 or NaN).
@@ -391,6 +403,11 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     // The store loop rebuilds each quad plane's descriptor (a few scalar
     // instructions) rather than keeping them alive across the frame; the empty asm
     // hides that the base is the one the loads used.
+    if (in_pad) {
+#pragma unroll
+        for (int k = NLO; k < NMAX; ++k)
+            if (k == N) sm[k] = Iw;
+    }
     uint32_t* sbase = a.m.samples + p0 * 4;
     asm volatile("" : "+s"(sbase));
 #pragma unroll
@@ -409,7 +426,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         if (differs(Tn, Tv)) a.m.T[p] = Tn;
         if (Sn.x != Sv.x || Sn.y != Sv.y) a.m.S[p] = Sn;
     }
-    a.m.last[p] = Iw;
+    if (!in_pad) a.m.last[p] = Iw;
     a.m.fire[a.t & 1u][p] = (uint8_t)fire;
 }
 
@@ -421,7 +438,10 @@ __device__ __forceinline__ void fill_pixel(const PbasStepArgs& a, int p) {
     const uint32_t Iw = (uint32_t)px[0] | ((uint32_t)px[1] << 8) | ((uint32_t)px[2] << 16) |
                         (depth_code(dmm, a.c.depth_max_mm) << 24);
     *reinterpret_cast<uint32_t*>(sample_byte(a.m.samples, a.npix, (int)a.t, p, 0)) = Iw;
-    a.m.last[p] = Iw;
+    if (a.m.last_in_pad)
+        *reinterpret_cast<uint32_t*>(sample_byte(a.m.samples, a.npix, a.c.N, p, 0)) = Iw;
+    else
+        a.m.last[p] = Iw;
     a.m.mask[p] = 0;
 }
 

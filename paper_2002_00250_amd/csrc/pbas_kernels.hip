@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void pbas_flush_kernel(PbasPlanes m, int H, in
     if (p >= H * W) return;
     const int y = p / W, x = p - y * W;
     const int64_t npix = (int64_t)H * W;
-    const uint32_t lastw = m.last[p];
+    const uint32_t lastw = m.last_in_pad ? *reinterpret_cast<const uint32_t*>(sample_byte(m.samples, npix, N, p, 0))
+                                         : m.last[p];
     const uint8_t* fire = m.fire[t_prev & 1u];
     for (int d = 0; d < 8; ++d) {
         const int qx = x + nb_dx(d), qy = y + nb_dy(d);

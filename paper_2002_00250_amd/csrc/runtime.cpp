@@ -407,6 +407,9 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         m->pb.fire[0] = m->dev + o_i0;
         m->pb.fire[1] = m->dev + o_i1;
         m->pb.mask = m->mask;
+        // the previous value in the first padding slot (the step kernels of N >= 33 read it
+        // there; smaller N keep the plane, see pbas_tile)
+        m->pb.last_in_pad = (m->pp.N & 3) != 0 && m->pp.N >= 33 ? 1 : 0;
         e = hipMemsetAsync(m->dev, 0, off, m->stream);
         if (e == hipSuccess) e = pbas_launch_init_state(m->pb, m->npix, m->pc, m->stream);
     }

@@ -354,6 +354,9 @@ fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, c
         fgs_destroy(m);
         return fail(FGS_ERR_OUT_OF_MEMORY, "host allocation");
     }
+    // The serving kernel keeps a PBAS pixel's previous value in its own plane (its one
+    // instance serves every N up to the class bound): set before the first frame.
+    if (algo == FGS_PBAS) m->pb.last_in_pad = 0;
     sr->model = m;
     sr->algo = algo;
     sr->H = H;
