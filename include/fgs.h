@@ -121,7 +121,10 @@ typedef struct fgs_gmm_params {
  * probability 1/T_j; R_j and T_j then adapt to d_bar = S_j/N within
  * [R_lower_j, inf) and [T_lower, T_upper].  Random words come from
  * Philox4x32-10 keyed by `seed` with counter (y*W + x, frame, call, 0).
- * Supported N: 2..64.
+ * Accepted: N in 2..64, min_matches in 1..N, R_lower_j > 0, 0 <= R_incdec < 1,
+ * R_scale > 0, 0 < T_lower <= T_upper, T_inc > 0 and T_dec > 0 (T moves by
+ * T_inc/d_bar or T_dec/d_bar, +-inf at d_bar = 0 before the clamp; a zero
+ * increment would make that 0/0; a fixed update period is T_lower = T_upper).
  */
 typedef struct fgs_pbas_params {
     uint32_t struct_size; /* = sizeof(fgs_pbas_params) */

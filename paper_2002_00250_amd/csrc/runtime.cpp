@@ -131,7 +131,7 @@ fgs_status check_pbas(const fgs_pbas_params& p) {
     if (p.min_matches < 1 || p.min_matches > p.N)
         return fail(FGS_ERR_INVALID_ARG, "min_matches = %d not in [1, N]", p.min_matches);
     if (!(p.T_lower > 0.f) || !(p.T_upper >= p.T_lower) || !(p.R_scale > 0.f) ||
-        !(p.R_incdec >= 0.f && p.R_incdec < 1.f) || !(p.T_inc >= 0.f) || !(p.T_dec >= 0.f) ||
+        !(p.R_incdec >= 0.f && p.R_incdec < 1.f) || !(p.T_inc > 0.f) || !(p.T_dec > 0.f) ||
         p.depth_max_mm < 1)
         return fail(FGS_ERR_INVALID_ARG, "PBAS parameter out of range");
     for (int j = 0; j < 4; ++j)

@@ -72,6 +72,14 @@ def test_errors_without_device(libfgs):
     with pytest.raises(fgs.FgsError) as e:
         fgs.fgs_create(fgs.FGS_PBAS, 10, 10, p)
     assert "N = 65" in str(e.value)
+    # a zero T increment would turn T_inc / d_bar into 0/0 where d_bar = 0: refused
+    for field, bad in (("T_inc", 0.0), ("T_dec", 0.0), ("T_lower", 0.0), ("min_matches", 0),
+                       ("R_incdec", 1.0)):
+        p = fgs.fgs_pbas_params_default()
+        setattr(p, field, bad)
+        with pytest.raises(fgs.FgsError) as e:
+            fgs.fgs_create(fgs.FGS_PBAS, 10, 10, p)
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG, field
     assert fgs.fgs_status_str(4) == "bad state"
     # a struct_size that is neither the current nor the earlier (52-byte) layout
     g = fgs.fgs_gmm_params_default()
