@@ -509,3 +509,20 @@ def test_error_paths():
     with pytest.raises(fgs.FgsError):
         fgs.Model(fgs.FGS_GMM, 8, 8, p)
     m.close()
+
+
+def test_copy_probe_copies_and_checks_alignment():
+    # the plain streaming copy that calibrates the bandwidth ceiling copies exactly
+    from paper_2002_00250_amd import fgs
+    n = (1 << 20) + 48
+    a = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+    b = torch.zeros(n + 32, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    fgs.fgs_copy_probe(a.data_ptr(), b.data_ptr() + 16, n, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(b[16:16 + n], a) and not b[:16].any() and not b[16 + n:].any()
+    for src, dst, nb in ((a.data_ptr() + 4, b.data_ptr(), 64), (a.data_ptr(), b.data_ptr() + 8, 64),
+                         (a.data_ptr(), b.data_ptr(), 40)):
+        with pytest.raises(fgs.FgsError) as e:
+            fgs.fgs_copy_probe(src, dst, nb, torch.cuda.current_stream().cuda_stream)
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG
