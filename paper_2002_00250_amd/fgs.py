@@ -458,6 +458,16 @@ class Model:
         if isinstance(rgb, np.ndarray):
             rgb = np.ascontiguousarray(rgb, np.uint8)
             depth = np.ascontiguousarray(depth, np.uint16)
+        else:
+            torch = self._torch
+            if rgb.dtype != torch.uint8 or rgb.dim() != 3 or rgb.shape[2] != 3 or \
+                    rgb.stride(2) != 1 or rgb.stride(1) != 3:
+                raise ValueError("rgb must be uint8 [H, W, 3] with packed pixels (rows may be strided)")
+            if depth.dtype not in (torch.int16, getattr(torch, "uint16", torch.int16)) or \
+                    depth.dim() != 2 or depth.stride(1) != 1:
+                raise ValueError("depth must be 16-bit [H, W] with packed pixels (rows may be strided)")
+        if tuple(rgb.shape[:2]) != (self.H, self.W):
+            raise ValueError(f"rgb is {tuple(rgb.shape[:2])}, the model is {(self.H, self.W)}")
         pr, wr = self._ptr_where(rgb)
         pd, wd = self._ptr_where(depth)
         if wr != wd:

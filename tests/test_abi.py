@@ -149,3 +149,22 @@ def test_gmm_state_pack_unpack_flags(diag):
     back = fgs.unpack_state(blob)
     for k in ("w_c", "mu_c", "v_c", "w_d", "mu_d", "v_d"):
         np.testing.assert_array_equal(back[k], st[k])
+
+
+def test_model_push_checks_tensor_arguments():
+    # argument checks of the binding, before any library call (CPU tensors suffice)
+    import torch
+    from paper_2002_00250_amd import fgs
+
+    class Unbound(fgs.Model):          # the checks only, no model behind them
+        def __init__(self):
+            self._torch, self.H, self.W = torch, 4, 6
+    m = Unbound()
+    bad = [(torch.zeros(4, 6, 3, dtype=torch.int16), torch.zeros(4, 6, dtype=torch.int16)),
+           (torch.zeros(4, 6, 3, dtype=torch.uint8), torch.zeros(4, 6, dtype=torch.int32)),
+           (torch.zeros(4, 3, 6, dtype=torch.uint8).permute(0, 2, 1), torch.zeros(4, 6, dtype=torch.int16)),
+           (torch.zeros(4, 6, 3, dtype=torch.uint8), torch.zeros(6, 4, dtype=torch.int16).t()),
+           (torch.zeros(5, 6, 3, dtype=torch.uint8), torch.zeros(5, 6, dtype=torch.int16))]
+    for rgb, dep in bad:
+        with pytest.raises(ValueError):
+            m.push(rgb, dep)
