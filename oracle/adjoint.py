@@ -46,7 +46,8 @@ from .gmm import GmmParams, background_count, first_match, fresh_mixture, sq_dis
 
 @dataclass
 class Decisions:
-    """Per frame and model: term [T,H,W] bool, argmin a [T,H,W], active [T,H,W],
+    """The discrete choices of the Sec. 3.1 step (R-08..R-12), recorded to be held fixed.
+    Per frame and model: term [T,H,W] bool, argmin a [T,H,W], active [T,H,W],
     kstar [T,H,W] (-1 = replaced), clamp [T,H,W], perm [T,K,H,W] (old index per new rank)."""
     term: np.ndarray
     argmin: np.ndarray
@@ -113,7 +114,8 @@ def _record_model_step(mix, X, active, alpha, lam2, T_bg, w_init, v_init, v_min)
 
 
 def record_window(rgb, depth, p: GmmParams, theta=None):
-    """fp32 forward over frames [T,H,W,3]/[T,H,W] from a fresh model, recording decisions.
+    """fp32 forward of the Sec. 3.1 GMM over frames [T,H,W,3]/[T,H,W] from a fresh model
+    (R-11, R-21), the same operations as oracle.gmm, recording the decisions.
 
     Returns (Z [T,H,W] float32, has_term [T,H,W] bool, colour Decisions, depth Decisions)."""
     T, H, W = depth.shape
@@ -181,7 +183,8 @@ def _delta(mu, v, X, a):
 
 def replay_window(rgb, depth, p: GmmParams, dc: Decisions, dd: Decisions, theta, dtype=np.float64,
                   keep_tape=False):
-    """Z_t(theta) with the recorded decisions held fixed.  Returns Z [T,H,W] (and the tape of
+    """Z_t(theta), the pre-update score of R-09, with the recorded decisions held fixed (the
+    continuous part of the Sec. 3.1 step).  Returns Z [T,H,W] (and the tape of
     pre-step means/variances if keep_tape)."""
     T, H, W = depth.shape
     alpha, lam, wd = (dtype(v) for v in theta)
@@ -208,7 +211,8 @@ def replay_window(rgb, depth, p: GmmParams, dc: Decisions, dd: Decisions, theta,
 
 
 def bce_loss_and_grad(Z, has, gt, t0=1, tau=1.0):
-    """Mean BCE of sigmoid(Z/tau) against gt (0/255) over frames t >= t0 where Z is defined.
+    """The window loss of R-21: mean BCE of sigmoid(Z/tau) against gt (0/255) over frames
+    t >= t0 where Z is defined.
     Returns (loss, dL/dZ)."""
     sel = np.zeros_like(has)
     sel[t0:] = has[t0:]
@@ -224,7 +228,9 @@ def bce_loss_and_grad(Z, has, gt, t0=1, tau=1.0):
 
 
 def reverse_gradient(rgb, depth, p: GmmParams, dc: Decisions, dd: Decisions, theta, dZ):
-    """Hand-written reverse sweep in fp64: dL/dtheta = (d alpha, d lambda, d w_d) given dL/dZ."""
+    """Hand-written reverse sweep in fp64 of replay_window (chain rule through the mean and
+    variance recursions of Sec. 3.1, choices fixed): dL/dtheta = (d alpha, d lambda, d w_d)
+    given dL/dZ."""
     f = np.float64
     alpha, lam, wd = (f(v) for v in theta)
     lam2 = lam * lam
@@ -297,6 +303,7 @@ def _reverse_model(mu, v, X, dec: Decisions, t, alpha, a_mu_out, a_v_out):
 
 
 def window_loss(rgb, depth, gt, p: GmmParams, dc, dd, has, theta, t0=1, tau=1.0):
+    """The R-21 loss of the fp64 replay at theta (decisions frozen)."""
     Z = replay_window(rgb, depth, p, dc, dd, theta, np.float64)
     return bce_loss_and_grad(Z, has, gt, t0, tau)[0]
 

@@ -27,7 +27,8 @@ DEPTH_MAX_MM = 10000
 
 
 def depth_q8(depth, depth_max_mm: int = DEPTH_MAX_MM) -> np.ndarray:
-    """uint16 depth in mm -> uint8 depth code (0 = invalid), as defined above."""
+    """uint16 depth in mm -> uint8 depth code (0 = invalid), as defined above (R-03,
+    from Sec. 4.2's 16-to-8-bit conversion)."""
     d = np.asarray(depth).astype(np.int64)
     m = int(depth_max_mm)
     q = (255 * d + m // 2) // m

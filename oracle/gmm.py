@@ -115,22 +115,27 @@ class GmmParams:
 
 @dataclass
 class Mixture:
-    """One model's per-pixel mixture: w [K,H,W], mu [K,C,H,W], v [K,H,W]."""
+    """One model's per-pixel mixture (Sec. 3.1: K Gaussians per pixel, each a weight, a
+    mean and a variance): w [K,H,W], mu [K,C,H,W], v [K,H,W]."""
     w: np.ndarray
     mu: np.ndarray
     v: np.ndarray
 
     def copy(self) -> "Mixture":
+        """An independent copy of the three arrays."""
         return Mixture(self.w.copy(), self.mu.copy(), self.v.copy())
 
 
 def fresh_mixture(K: int, C: int, H: int, W: int, v_init, dtype) -> Mixture:
+    """The model before the first frame (R-11; Sec. 3.1 gives no initialisation): every
+    weight 0, every mean 0, every variance v_init."""
     return Mixture(np.zeros((K, H, W), dtype), np.zeros((K, C, H, W), dtype),
                    np.full((K, H, W), v_init, dtype))
 
 
 def fresh_mixture_diag(K: int, C: int, H: int, W: int, v_init, dtype) -> Mixture:
-    """A mixture with a variance per channel: v [K,C,H,W]."""
+    """A mixture with a variance per channel (R-05', the other reading of Sec. 3.1's
+    three-variances remark): v [K,C,H,W]."""
     return Mixture(np.zeros((K, H, W), dtype), np.zeros((K, C, H, W), dtype),
                    np.full((K, C, H, W), v_init, dtype))
 
@@ -282,7 +287,8 @@ def update_mixture(mix: Mixture, X: np.ndarray, q: np.ndarray, active: np.ndarra
 
 
 class GmmRef:
-    """The RGB-D GMM over an H x W image.  ``step(rgb, depth) -> mask``."""
+    """The RGB-D GMM over an H x W image (Sec. 3.1: a colour and a depth mixture per
+    pixel, combined in the decision).  ``step(rgb, depth) -> mask``."""
 
     def __init__(self, H: int, W: int, params: GmmParams | None = None, dtype=np.float32):
         self.p = params or GmmParams()
@@ -300,6 +306,7 @@ class GmmRef:
         self.last_has_term = None
 
     def constants(self):
+        """The parameters in the working precision (each rounded once, as the kernels do)."""
         f = self.dtype.type
         p = self.p
         return dict(alpha=f(p.alpha), lam=f(p.lam), T_bg=f(p.T_bg), w_init=f(p.w_init),
@@ -307,6 +314,9 @@ class GmmRef:
                     v_min_d=f(p.v_min_d), w_depth=f(p.w_depth))
 
     def step(self, rgb: np.ndarray, depth: np.ndarray) -> np.ndarray:
+        """One frame (Sec. 3.1): both mixtures' distances, the decision on the pre-update
+        models (R-08, R-09, or R-09' with `decision` 1), then each active model's match,
+        update, replacement, renormalisation and ranking (R-06..R-08, R-10, R-12)."""
         c = self.constants()
         f = self.dtype.type
         lam2 = c["lam"] * c["lam"]
@@ -355,10 +365,12 @@ class GmmRef:
 
     # State in the library's canonical plane order (see include/fgs.h).
     def state_planes(self) -> dict:
+        """The state in the library's serialised plane order (fgs_copy_state's payload)."""
         return dict(w_c=self.colour.w, mu_c=self.colour.mu, v_c=self.colour.v,
                     w_d=self.depth.w, mu_d=self.depth.mu[:, 0], v_d=self.depth.v, t=self.t)
 
     def set_state_planes(self, st: dict) -> None:
+        """Replace the state from planes in that order (fgs_set_state's payload)."""
         dt = self.dtype
         self.colour = Mixture(np.array(st["w_c"], dt), np.array(st["mu_c"], dt), np.array(st["v_c"], dt))
         self.depth = Mixture(np.array(st["w_d"], dt), np.array(st["mu_d"], dt)[:, None],

@@ -10,6 +10,7 @@ import numpy as np
 
 
 def confusion(mask, gt):
+    """(TP, TN, FP, FN) of a mask against ground truth, foreground = positive (Sec. 5)."""
     m = np.asarray(mask) != 0
     g = np.asarray(gt) != 0
     tp = int(np.count_nonzero(m & g))
@@ -24,9 +25,11 @@ def _div(a, b):
 
 
 def indicators(tp: int, tn: int, fp: int, fn: int) -> dict:
+    """The Sec. 5 indicators from the counts: PWC, FNR, FPR and the similarity Si."""
     return dict(PWC=100.0 * _div(fn + fp, tp + fn + fp + tn), FNR=_div(fn, tp + fn),
                 FPR=_div(fp, fp + tn), Si=_div(tp, tp + fp + fn))
 
 
 def score(mask, gt) -> dict:
+    """The Sec. 5 indicators of one mask."""
     return indicators(*confusion(mask, gt))

@@ -81,7 +81,7 @@ class PbasParams:
 
 
 def pbas_draws(H: int, W: int, t: int, seed: int, origin=None):
-    """Philox words for frame t: (w0, w1), each uint32 [H, W, 4] (word j -> channel j).
+    """Philox words for frame t (R-17): (w0, w1), each uint32 [H, W, 4] (word j -> channel j).
     The counter's first word is the pixel's linear index y * W_img + x in the whole image;
     ``origin = (y0, x0, W_img)`` places this H x W array as a window of a larger image."""
     k0, k1 = seed_key(seed)
@@ -100,7 +100,8 @@ def pbas_draws(H: int, W: int, t: int, seed: int, origin=None):
 
 
 class PbasRef:
-    """The RGB-D PBAS over an H x W image.  ``step(rgb, depth) -> mask``."""
+    """The RGB-D PBAS over an H x W image (Sec. 3.2: samples of RGB and depth, each
+    component segmented and updated on its own, R-14).  ``step(rgb, depth) -> mask``."""
 
     def __init__(self, H: int, W: int, params: PbasParams | None = None, origin=None):
         """``origin = (y0, x0, W_img)``: this model is the window of rows y0.. and columns
@@ -122,13 +123,18 @@ class PbasRef:
         self.last_draws = None
 
     def frame_value(self, rgb, depth) -> np.ndarray:
-        """I(x, t): RGB bytes plus the depth code (0 where depth is invalid)."""
+        """I(x, t): RGB bytes plus the depth code (0 where depth is invalid): the RGBD8
+        sample word of Sec. 4.2 with the depth code of R-03."""
         I = np.empty((self.H, self.W, 4), np.uint8)
         I[..., :3] = rgb
         I[..., 3] = depth_q8(depth, self.p.depth_max_mm)
         return I
 
     def step(self, rgb: np.ndarray, depth: np.ndarray) -> np.ndarray:
+        """One frame (Sec. 3.2): the fill phase for the first N frames (R-16), else the
+        per-channel segmentation against the previous model (R-14, R-15), the self-update
+        (R-18) and neighbour update (R-19) driven by the Philox words (R-17), and the R/T
+        adaptation (R-20)."""
         p = self.p
         H, W, N = self.H, self.W, p.N
         I = self.frame_value(rgb, depth)
@@ -207,12 +213,14 @@ class PbasRef:
 
     # State in the library's canonical plane order (see include/fgs.h).
     def state_planes(self) -> dict:
+        """The state in the library's serialised plane order (fgs_copy_state's payload)."""
         return dict(samples=np.ascontiguousarray(self.samples).view(np.uint32)[..., 0],
                     dhist=np.ascontiguousarray(self.D).view(np.uint32)[..., 0],
                     R=np.moveaxis(self.R, -1, 0).copy(), T=np.moveaxis(self.T, -1, 0).copy(),
                     S=np.moveaxis(self.S, -1, 0).astype(np.uint16), t=self.t)
 
     def set_state_planes(self, st: dict) -> None:
+        """Replace the state from planes in that order (fgs_set_state's payload)."""
         N, H, W = self.p.N, self.H, self.W
         self.samples = np.ascontiguousarray(st["samples"], np.uint32).view(np.uint8).reshape(N, H, W, 4).copy()
         self.D = np.ascontiguousarray(st["dhist"], np.uint32).view(np.uint8).reshape(N, H, W, 4).copy()

@@ -34,7 +34,8 @@ ROUNDS = 10
 
 
 def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
-    """Vectorised Philox4x32-10.  Counter words are broadcastable uint32-valued arrays.
+    """Vectorised Philox4x32-10 (Salmon et al., SC'11).  Counter words are broadcastable
+    uint32-valued arrays.
 
     Returns four uint32 arrays (the output words x0..x3).
     """
