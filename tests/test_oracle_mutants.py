@@ -14,12 +14,14 @@ import oracle.gmm
 import oracle.metrics
 import oracle.pbas
 import oracle.philox
+import oracle.postfilter
 import test_oracle_adjoint
 import test_oracle_depth
 import test_oracle_gmm
 import test_oracle_metrics
 import test_oracle_pbas
 import test_oracle_philox
+import test_oracle_postfilter
 
 
 def _mutant(func, old, new):
@@ -141,6 +143,16 @@ OTHER_MUTANTS = [
      "ys = (np.arange(H, dtype=np.int64) * Hd) // H", test_oracle_depth),
     ("false positives and negatives swapped", oracle.metrics, "indicators",
      "FNR=_div(fn, tp + fn)", "FNR=_div(fp, tp + fn)", test_oracle_metrics),
+    ("median border padded with zeros", oracle.postfilter, "median_mask",
+     'np.pad(m, r, mode="edge")', 'np.pad(m, r, mode="constant")', test_oracle_postfilter),
+    ("median takes the next-larger element", oracle.postfilter, "median_mask",
+     "[..., (k * k) // 2]", "[..., (k * k) // 2 + 1]", test_oracle_postfilter),
+    ("median treats only values >= 128 as foreground", oracle.postfilter, "median_mask",
+     "np.asarray(mask) != 0", "np.asarray(mask) >= 128", test_oracle_postfilter),
+    ("median window one row short", oracle.postfilter, "median_mask",
+     "padded[a:b + 2 * r]", "padded[a + 1:b + 2 * r]", test_oracle_postfilter),
+    ("median window anchored at its left edge", oracle.postfilter, "median_mask",
+     'np.pad(m, r, mode="edge")', 'np.pad(m, ((r, r), (0, 2 * r)), mode="edge")', test_oracle_postfilter),
 ]
 
 
@@ -192,5 +204,6 @@ def test_philox_pin_catches_swapped_key_words(monkeypatch, rocrand_probe):
 
 
 def test_unmutated_oracle_passes_its_pins():
-    for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics, test_oracle_adjoint):
+    for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics, test_oracle_adjoint,
+                test_oracle_postfilter):
         assert _caught(mod) is None, mod.__name__
