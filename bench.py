@@ -304,10 +304,15 @@ def adjoint_main(args):
     print(json.dumps(out), flush=True)
 
 
+MEDIAN_R = 4   # the base PBAS method's 9x9 median window
+
+
 def eval_main(args):
     """Evaluation counters on 1280x720: per-frame confusion counts of a GMM K=5 model's
     mask against ground truth accumulated on the device, the Sec. 5 indicators from them,
-    and the counting kernel timed on its own (2 B/px: mask + ground truth)."""
+    and the counting kernel timed on its own (2 B/px: mask + ground truth).  Beside them,
+    the median post-filter: the indicators of the 9x9-filtered masks and the filter kernel
+    timed on its own at radii 1, 4 and 7 (2 B/px: mask in, mask out)."""
     import torch
     from paper_2002_00250_amd import fgs
     from synth import Scene, preset
@@ -322,11 +327,27 @@ def eval_main(args):
     gp = fgs.fgs_gmm_params_default()
     gp.Kc, gp.Kd = KC, KD
     m = fgs.Model(fgs.FGS_GMM, H, W, gp, stream=stream)
+    med = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    med_counts = np.zeros(4, np.int64)
     for t in range(len(frames)):
         fgs.fgs_push_frame(m.handle, rgb[t].data_ptr(), 3 * W, dep[t].data_ptr(), 2 * W, fgs.FGS_MEM_DEVICE)
         if t >= 8:
             m.eval_accumulate(gt[t])
+            fgs.fgs_mask_median(m.mask_ptr, W, med.data_ptr(), W, H, W, MEDIAN_R, stream.cuda_stream)
+            fm, g = med.cpu().numpy() != 0, gt[t].cpu().numpy() != 0
+            med_counts += [np.sum(fm & g), np.sum(~fm & ~g), np.sum(fm & ~g), np.sum(~fm & g)]
     counts = m.eval_read(reset=True)
+    med_us = {}
+    for r in (1, MEDIAN_R, 7):
+        for _ in range(20):
+            fgs.fgs_mask_median(m.mask_ptr, W, med.data_ptr(), W, H, W, r, stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fgs.fgs_mask_median(m.mask_ptr, W, med.data_ptr(), W, H, W, r, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        med_us[r] = e0.elapsed_time(e1) / args.steps * 1e3
     K = args.steps
     g_last = gt[-1].data_ptr()        # one stream throughout: the raw call, no stream waits
     for _ in range(20):
@@ -344,6 +365,10 @@ def eval_main(args):
            "unit": "us", "higher_is_better": False, "n_gpus": 1, "steps": K,
            "GBs": round(2 * H * W / (us * 1e-6) / 1e9, 1),
            "counts_tp_tn_fp_fn": list(counts), "indicators": {k: round(v, 5) for k, v in ind.items()},
+           "median_filter": {"us_per_frame": {f"r{r}": round(v, 3) for r, v in med_us.items()},
+                             "GBs": {f"r{r}": round(2 * H * W / (v * 1e-6) / 1e9, 1) for r, v in med_us.items()},
+                             f"indicators_r{MEDIAN_R}": {k: round(v, 5) for k, v in
+                                                         indicators_from([int(x) for x in med_counts]).items()}},
            "dtype": "u8", "data": "synthetic",
            "config": {"workload": "GMM Kc=Kd=5 1280x720, frames 8..31 scored against ground truth"}}
     print(json.dumps(out), flush=True)

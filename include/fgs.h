@@ -244,6 +244,30 @@ fgs_status fgs_eval_accumulate(fgs_model* m, const uint8_t* gt, int64_t gt_strid
 fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset);
 
 /*
+ * Median post-filter of a binary mask.  The paper's method leaves its masks
+ * unfiltered (Sec. 3); the base PBAS method it builds on smooths its output with a
+ * median filter, and this call offers that step for any mask, e.g. the one
+ * fgs_mask_device_ptr returns.
+ *
+ * dst(y, x) = 255 if more than half of the (2r+1) x (2r+1) pixels of src centred on
+ * (y, x) are nonzero, else 0: the median of the window, reading a pixel as
+ * background (0) or foreground (nonzero, taken as 255).  Window pixels outside
+ * the image repeat the nearest edge pixel (replicated border), so every pixel,
+ * edges included, sees (2r+1)^2 values.  radius 0 copies the mask as 0/255.
+ *
+ * src and dst are device buffers of H rows of W bytes, rows src_stride and
+ * dst_stride >= W bytes apart; the caller owns both, and the byte ranges they
+ * span must not overlap (the filter is not in place).  Runs on hip_stream (NULL:
+ * the null stream) and returns after enqueueing: src is read and dst written in
+ * stream order.  H = 0 or W = 0 is an empty image and enqueues nothing.
+ * INVALID_ARG for NULL buffers of a nonempty image, H or W negative or above
+ * 2^30, H * W above 2^34, a stride below W or above 2^32, radius outside 0..7,
+ * or overlapping ranges; DEVICE if the launch fails.
+ */
+fgs_status fgs_mask_median(const uint8_t* src, int64_t src_stride, uint8_t* dst, int64_t dst_stride,
+                           int32_t H, int32_t W, int32_t radius, void* hip_stream);
+
+/*
  * Model state, serialised in a fixed layout (little-endian):
  *   header (64 bytes): uint32 magic 0x53534746 ("FGSS"), uint32 version (1),
  *     uint32 algo, int32 H, int32 W, int32 A, int32 B, int32 flags,

@@ -16,6 +16,7 @@ Modules
 ``gmm``       RGB-D Gaussian mixture model step (Sec. 3.1)
 ``pbas``      RGB-D Pixel-Based Adaptive Segmenter step (Sec. 3.2)
 ``metrics``   PWC / FNR / FPR / Si quality indicators (Sec. 5)
+``postfilter`` median post-filter of a binary mask (base PBAS method's smoothing)
 
 Floating point follows IEEE binary32 (or binary64 for the gradient reference)
 with every operation rounded separately, in the order written in each

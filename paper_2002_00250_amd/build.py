@@ -20,7 +20,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfgs.so")
-SOURCES = ["gmm_kernels.hip", "gmm_window.hip", "pbas_kernels.hip", "serve_kernels.hip", "diag_kernels.hip", "eval_kernels.hip",
+SOURCES = ["gmm_kernels.hip", "gmm_window.hip", "pbas_kernels.hip", "serve_kernels.hip", "diag_kernels.hip", "eval_kernels.hip", "postfilter_kernels.hip",
            "runtime.cpp", "server.cpp"]
 ARCH = os.environ.get("FGS_OFFLOAD_ARCH", "gfx950")
 

@@ -19,6 +19,7 @@
 #include "fgs.h"
 #include "fgs_internal.h"
 #include "model.h"
+#include "postfilter.h"
 
 using namespace fgs;
 
@@ -939,6 +940,27 @@ fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w) {
     (void)hipFree(w->dev);
     if (w->own_stream) (void)hipStreamDestroy(w->stream);
     delete w;
+    return FGS_OK;
+}
+
+fgs_status fgs_mask_median(const uint8_t* src, int64_t src_stride, uint8_t* dst, int64_t dst_stride,
+                           int32_t H, int32_t W, int32_t radius, void* hip_stream) {
+    constexpr int32_t kMaxSide = 1 << 30;
+    constexpr int64_t kMaxStride = (int64_t)1 << 32;
+    if (H < 0 || W < 0 || H > kMaxSide || W > kMaxSide || (int64_t)H * W > ((int64_t)1 << 34))
+        return fail(FGS_ERR_INVALID_ARG, "median: image %d x %d outside 0..2^30 per side, 2^34 pixels", H, W);
+    if (radius < 0 || radius > kMedRadiusMax)
+        return fail(FGS_ERR_INVALID_ARG, "median: radius %d outside 0..%d", radius, kMedRadiusMax);
+    if (H == 0 || W == 0) return FGS_OK;
+    if (!src || !dst) return fail(FGS_ERR_INVALID_ARG, "median: NULL buffer");
+    if (src_stride < W || dst_stride < W || src_stride > kMaxStride || dst_stride > kMaxStride)
+        return fail(FGS_ERR_INVALID_ARG, "median: strides %lld, %lld outside W..2^32", (long long)src_stride,
+                    (long long)dst_stride);
+    const uintptr_t s0 = (uintptr_t)src, s1 = s0 + (uintptr_t)((int64_t)(H - 1) * src_stride + W);
+    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + (uintptr_t)((int64_t)(H - 1) * dst_stride + W);
+    if (s0 < d1 && d0 < s1) return fail(FGS_ERR_INVALID_ARG, "median: source and destination overlap");
+    hipError_t e = post_launch_median(src, src_stride, dst, dst_stride, H, W, radius, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "median kernel: %s", hipGetErrorString(e));
     return FGS_OK;
 }
 

@@ -125,6 +125,7 @@ def _load():
         "fgs_server_destroy": (S, [c_void_p]),
         "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
         "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
+        "fgs_mask_median": (S, [c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -346,6 +347,35 @@ def fgs_copy_probe(src: int, dst: int, nbytes: int, hip_stream: int | None = Non
     _check(_load().fgs_copy_probe(c_void_p(src), c_void_p(dst), nbytes, c_void_p(hip_stream or 0)))
 
 
+def fgs_mask_median(src: int, src_stride: int, dst: int, dst_stride: int, H: int, W: int, radius: int,
+                    hip_stream: int | None = None) -> None:
+    _check(_load().fgs_mask_median(c_void_p(src), src_stride, c_void_p(dst), dst_stride, H, W, radius,
+                                   c_void_p(hip_stream or 0)))
+
+
+def median_mask(mask, radius: int, out=None):
+    """Median post-filter of a binary device mask (uint8 [H, W] tensor on the GPU, rows
+    contiguous): 255 where more than half of the (2r+1)^2 window is nonzero, border pixels
+    replicated.  Runs on torch's current stream; returns `out` (allocated if None)."""
+    import torch
+    for name, t in (("mask", mask), ("out", out)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.uint8 or t.dim() != 2:
+            raise ValueError(f"{name} must be a uint8 [H, W] tensor on the GPU")
+        if t.shape[1] > 1 and t.stride(1) != 1:
+            raise ValueError(f"{name} rows must be contiguous")
+    if out is None:
+        out = torch.empty(mask.shape, dtype=torch.uint8, device=mask.device)
+    elif tuple(out.shape) != tuple(mask.shape):
+        raise ValueError("out must have the mask's shape")
+    H, W = mask.shape
+    stream = torch.cuda.current_stream(mask.device).cuda_stream
+    fgs_mask_median(mask.data_ptr(), max(mask.stride(0), W), out.data_ptr(), max(out.stride(0), W), H, W,
+                    radius, stream)
+    return out
+
+
 # ---------------------------------------------------------------- state layout
 def unpack_state(blob: np.ndarray) -> dict:
     """Split a serialised state (see fgs_copy_state) into named numpy planes."""
@@ -423,6 +453,12 @@ class Model:
         self.handle = fgs_create(algo, H, W, params, handle)
         self._mask_ptr = fgs_mask_device_ptr(self.handle)
         self._ext = None
+
+    @property
+    def mask_ptr(self) -> int:
+        """Device address of the model's mask (H rows of W bytes, rows W apart), rewritten
+        by every push in the model's stream order (fgs_mask_device_ptr)."""
+        return self._mask_ptr
 
     def _model_stream(self):
         if self._ext is None:

@@ -64,6 +64,15 @@ def test_defaults_match_oracle_readings(libfgs):
 
 def test_errors_without_device(libfgs):
     from paper_2002_00250_amd import fgs
+    # the median filter checks its arguments before touching a device; an empty image is a no-op
+    for args in [(16, 0, 16, 0, 4, 4, 8), (16, 4, 16, 4, 4, 4, -1), (16, 3, 32, 4, 4, 4, 1),
+                 (16, 4, 32, 4, -1, 4, 1), (0, 4, 32, 4, 4, 4, 1), (16, 4, 18, 4, 4, 4, 1),
+                 (16, 1 << 30, 1 << 40, 1 << 30, 1 << 30, 1 << 30, 1)]:
+        with pytest.raises(fgs.FgsError) as e:
+            fgs.fgs_mask_median(*args)
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG, args
+    fgs.fgs_mask_median(0, 0, 0, 0, 0, 7, 3)
+    fgs.fgs_mask_median(0, 0, 0, 0, 7, 0, 3)
     with pytest.raises(fgs.FgsError) as e:
         fgs.fgs_create(fgs.FGS_GMM, 0, 10)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG
