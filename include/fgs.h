@@ -406,7 +406,8 @@ fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w);
  *   `max_streams` streams; GMM streams must use Kc = Kd = gmm_K (3 or 5), PBAS
  *   streams N <= pbas_N_max (<= 40).  Uses the current device.
  * fgs_server_open: admit a stream (params as in fgs_create).  BUSY when the
- *   budget or the stream slots would be exceeded (nothing is allocated then);
+ *   budget or the stream slots would be exceeded, also between opens that run
+ *   concurrently (nothing stays allocated then);
  *   UNSUPPORTED for a K or N outside the server's classes, or for GMM per-channel
  *   colour variances (var_mode 1); the rate and decision variants are served.
  * fgs_server_submit: copy one host frame (dense rgb uint8[H][W][3], depth
@@ -418,9 +419,12 @@ fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w);
  *   forever; else BUSY on timeout), copy its mask (host uint8[H][W]; NULL to
  *   skip), report its latency (completion - arrival, seconds) and release the
  *   slot.  BAD_STATE if the frame was dropped by fgs_server_close, DEVICE after
- *   a device error.
+ *   a device error.  A ticket is collected once: INVALID_ARG for a ticket that
+ *   was never issued or that another wait already collected (also when that
+ *   wait ran concurrently).
  * fgs_server_close: stop a stream; its frame in flight finishes, queued frames
- *   are dropped, its device memory returns to the budget.
+ *   are dropped, its device memory returns to the budget, and its pinned host
+ *   ring is freed once its last ticket is collected.
  * fgs_server_get_stats: since creation or the last fgs_server_reset_stats:
  *   completed frames, batches, mean frames per batch, p50 / p99 / max latency,
  *   completed pixel-frames per second, budget use.  Set struct_size first.

@@ -63,6 +63,7 @@ struct Stream {
     size_t rgb_bytes = 0, in_bytes = 0, dev_bytes = 0;
     Slot slots[kQueue];
     int next_submit = 0, next_run = 0;
+    int copying = 0;  // submits copying into a slot with the lock released
     bool inflight = false, closed = false;
 };
 
@@ -91,6 +92,7 @@ struct fgs_server {
     std::vector<Stream*> closed;
     std::map<uint64_t, std::pair<Stream*, int>> tickets;
     int next_id = 1;
+    int opening = 0;  // opens past the stream-count check, not yet admitted or refused
     uint64_t next_ticket = 1;
     std::deque<Batch*> completion;
     std::vector<hipEvent_t> event_pool;
@@ -278,6 +280,35 @@ void free_stream_host(Stream* st) {
     }
 }
 
+// A closed stream's host buffers are freed once nothing refers to them: no ticket
+// (every slot collected) and no submit still copying into a slot (caller holds s->mu).
+void reclaim_if_idle(fgs_server* s, Stream* st) {
+    if (!st->closed || st->copying != 0) return;
+    for (const Slot& sl : st->slots)
+        if (sl.state != kFree) return;
+    auto it = std::find(s->closed.begin(), s->closed.end(), st);
+    if (it == s->closed.end()) return;
+    s->closed.erase(it);
+    free_stream_host(st);
+    delete st;
+}
+
+// Holds one of the server's max_streams places from the count check until the stream
+// is admitted (release_locked) or the open fails (destructor).
+struct OpenReservation {
+    fgs_server* s;
+    bool held = true;
+    void release_locked() {
+        if (held) s->opening -= 1;
+        held = false;
+    }
+    ~OpenReservation() {
+        if (!held) return;
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->opening -= 1;
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -337,15 +368,24 @@ fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, c
     } else if (algo == FGS_PBAS) {
         fgs_pbas_params p;
         fgs_pbas_params_default(&p);
-        if (params) std::memcpy(&p, params, sizeof p);
+        if (params) {
+            uint32_t size = 0;
+            std::memcpy(&size, params, sizeof size);
+            if (size != sizeof p)
+                return fail(FGS_ERR_INVALID_ARG, "fgs_pbas_params.struct_size %u != %zu", size, sizeof p);
+            std::memcpy(&p, params, sizeof p);
+        }
         if (p.N > s->pbas_nmax) return fail(FGS_ERR_UNSUPPORTED, "this server runs PBAS streams with N <= %d", s->pbas_nmax);
     } else {
         return fail(FGS_ERR_INVALID_ARG, "unknown algo %d", (int)algo);
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if ((int)s->streams.size() >= s->max_streams) return fail(FGS_ERR_BUSY, "all %d stream slots in use", s->max_streams);
+        if ((int)s->streams.size() + s->opening >= s->max_streams)
+            return fail(FGS_ERR_BUSY, "all %d stream slots in use", s->max_streams);
+        s->opening += 1;
     }
+    OpenReservation place{s};
     fgs_model* m = nullptr;
     fgs_status st = fgs_create(algo, H, W, params, s->compute, &m);
     if (st != FGS_OK) return st;
@@ -392,6 +432,7 @@ fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, c
         delete sr;
         return fail(FGS_ERR_OUT_OF_MEMORY, "stream buffers: %s", hipGetErrorString(e));
     }
+    place.release_locked();
     sr->id = s->next_id++;
     s->streams[sr->id] = sr;
     *stream_id = sr->id;
@@ -415,13 +456,18 @@ fgs_status fgs_server_submit(fgs_server* s, int32_t id, const uint8_t* rgb, cons
     st->next_submit = (k + 1) % kQueue;
     s->tickets[sl.ticket] = {st, k};
     *ticket = sl.ticket;
+    st->copying += 1;
     lk.unlock();
     std::memcpy(sl.h_in, rgb, (size_t)st->npix * 3);
     std::memcpy(sl.h_in + st->rgb_bytes, depth, (size_t)st->npix * 2);
     lk.lock();
-    // A close that ran during the copy marked the slot dropped (its host buffers stay
-    // until destroy): the ticket stays valid and its wait reports the drop.
-    if (sl.state != kFilling) return FGS_OK;
+    st->copying -= 1;
+    // A close that ran during the copy marked the slot dropped (the copy counter kept its
+    // host buffers): the ticket stays valid and its wait reports the drop.
+    if (sl.state != kFilling) {
+        reclaim_if_idle(s, st);
+        return FGS_OK;
+    }
     sl.state = kQueued;
     s->cv_sched.notify_one();
     return FGS_OK;
@@ -431,21 +477,32 @@ fgs_status fgs_server_wait(fgs_server* s, uint64_t ticket, uint8_t* mask, double
                            int32_t timeout_ms) {
     if (!s) return fail(FGS_ERR_INVALID_ARG, "server is NULL");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->tickets.find(ticket);
-    if (it == s->tickets.end()) return fail(FGS_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
-    Stream* st = it->second.first;
-    Slot& sl = st->slots[it->second.second];
-    auto done = [&] { return sl.state == kDone || sl.state == kDropped; };
+    if (s->tickets.find(ticket) == s->tickets.end())
+        return fail(FGS_ERR_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
+    // Look the ticket up again on every wake-up: another wait may have collected it, and
+    // its stream may then be gone.
+    auto done = [&] {
+        auto f = s->tickets.find(ticket);
+        if (f == s->tickets.end()) return true;
+        const SlotState q = f->second.first->slots[f->second.second].state;
+        return q == kDone || q == kDropped;
+    };
     if (timeout_ms < 0) {
         s->cv_done.wait(lk, done);
     } else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done)) {
         return fail(FGS_ERR_BUSY, "ticket %llu not finished", (unsigned long long)ticket);
     }
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end())
+        return fail(FGS_ERR_INVALID_ARG, "ticket %llu was collected by another wait", (unsigned long long)ticket);
+    Stream* st = it->second.first;
+    Slot& sl = st->slots[it->second.second];
     const bool ok = sl.state == kDone;
     if (ok && mask) std::memcpy(mask, sl.h_mask, (size_t)st->npix);
     if (latency_s) *latency_s = ok ? sl.latency : -1.0;
     sl.state = kFree;
     s->tickets.erase(it);
+    reclaim_if_idle(s, st);
     if (ok) return FGS_OK;
     return s->device_error ? fail(FGS_ERR_DEVICE, "frame lost to a device error")
                            : fail(FGS_ERR_BAD_STATE, "frame dropped: its stream was closed");
@@ -464,7 +521,8 @@ fgs_status fgs_server_close(fgs_server* s, int32_t id) {
         if (sl.state == kQueued || sl.state == kFilling) sl.state = kDropped;
     s->used -= st->dev_bytes;
     free_stream_device(st);
-    s->closed.push_back(st);  // host buffers stay until every ticket is collected / destroy
+    s->closed.push_back(st);  // host buffers stay until every ticket is collected
+    reclaim_if_idle(s, st);
     s->cv_done.notify_all();
     return FGS_OK;
 }

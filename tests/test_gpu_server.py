@@ -213,6 +213,101 @@ def test_close_during_submit_never_strands_a_ticket():
     log(f"close during submit: {outcomes}")
 
 
+def test_concurrent_opens_respect_max_streams():
+    # opens racing each other: the server admits exactly max_streams of them (its batch
+    # descriptors hold max_streams entries), refuses the rest as BUSY, and admits again
+    # after a close
+    import threading
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    for rnd in range(3):
+        srv = Server(1 << 30, 3)
+        gate = threading.Barrier(8)
+        got = {"ok": [], "busy": 0}
+        lock = threading.Lock()
+
+        def opener(j):
+            gate.wait()
+            try:
+                sid = srv.open(fgs.FGS_GMM if j % 2 else fgs.FGS_PBAS, 48, 64,
+                               _params(fgs.FGS_GMM if j % 2 else fgs.FGS_PBAS))
+                with lock:
+                    got["ok"].append(sid)
+            except fgs.FgsError as err:
+                assert err.status == fgs.FGS_ERR_BUSY, err.status
+                with lock:
+                    got["busy"] += 1
+        ths = [threading.Thread(target=opener, args=(j,)) for j in range(8)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        assert len(got["ok"]) == 3 and got["busy"] == 5, got
+        assert srv.stats()["streams_open"] == 3
+        fr = _frames(48, 64, 2, seed=rnd)
+        for sid in got["ok"]:                       # every admitted stream serves a frame
+            srv.wait(srv.submit(sid, *fr[0]), timeout_ms=10000)
+        srv.close_stream(got["ok"][0])
+        srv.open(fgs.FGS_GMM, 48, 64, _params(fgs.FGS_GMM))
+        with pytest.raises(fgs.FgsError) as e:
+            srv.open(fgs.FGS_GMM, 48, 64, _params(fgs.FGS_GMM))
+        assert e.value.status == fgs.FGS_ERR_BUSY
+        srv.destroy()
+
+
+def test_ticket_collected_once_and_closed_streams_released():
+    # a ticket is collected by one wait; a second wait (after it, or racing it) reports an
+    # unknown ticket instead of touching a released stream; streams closed with frames
+    # pending are released once their tickets are collected, over many open/close cycles
+    import threading
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    srv = Server(1 << 30, 4)
+    fr = _frames(48, 64, 3, seed=9)
+    sid = srv.open(fgs.FGS_PBAS, 48, 64, _params(fgs.FGS_PBAS))
+    tk = srv.submit(sid, *fr[0])
+    srv.wait(tk, timeout_ms=10000)
+    with pytest.raises(fgs.FgsError) as e:
+        srv.wait(tk, timeout_ms=100)
+    assert e.value.status == fgs.FGS_ERR_INVALID_ARG
+    for cycle in range(40):
+        sid2 = srv.open(fgs.FGS_GMM, 48, 64, _params(fgs.FGS_GMM))
+        tks = [srv.submit(sid2, *fr[i]) for i in range(3)]
+        res = {"ok": 0, "other": []}
+        lock = threading.Lock()
+
+        def waiter(t):
+            try:
+                srv.wait(t, timeout_ms=10000)
+                with lock:
+                    res["ok"] += 1
+            except fgs.FgsError as err:
+                with lock:
+                    res["other"].append(err.status)
+        ths = [threading.Thread(target=waiter, args=(tks[0],)) for _ in range(2)]
+        for t in ths:
+            t.start()
+        srv.close_stream(sid2)
+        for t in ths:
+            t.join()
+        # the first frame is done or dropped: one wait collects it, the other finds it gone
+        assert res["ok"] + res["other"].count(fgs.FGS_ERR_BAD_STATE) == 1, res
+        assert res["other"].count(fgs.FGS_ERR_INVALID_ARG) == 1, res
+        for t in tks[1:]:
+            try:
+                srv.wait(t, timeout_ms=10000)
+            except fgs.FgsError as err:
+                assert err.status == fgs.FGS_ERR_BAD_STATE, err.status
+    assert srv.stats()["streams_open"] == 1
+    srv.wait(srv.submit(sid, *fr[1]), timeout_ms=10000)
+    bad = fgs.fgs_pbas_params_default()
+    bad.struct_size = 8                                   # wrong struct size: refused, nothing read
+    with pytest.raises(fgs.FgsError) as e:
+        srv.open(fgs.FGS_PBAS, 48, 64, bad)
+    assert e.value.status == fgs.FGS_ERR_INVALID_ARG
+    srv.destroy()
+
+
 def test_32_streams_30fps_mixed_resolution():
     # 12x 424x240, 12x 640x480, 8x 1280x720; even streams GMM K=5, odd PBAS N=20;
     # frames at 30 fps, random phase, +-5 ms jitter.  p99 latency below one frame period,
