@@ -69,6 +69,26 @@ def test_no_depth_means_no_depth_weight_gradient():
     assert np.isclose(g[1], float((dZ * (-2 * p.lam) * dc.term).sum()), rtol=1e-12)
 
 
+def test_lambda_and_depth_weight_gradients_in_closed_form():
+    # with the choices frozen, Z is affine in w_d with slope delta_d - lambda^2 where the depth
+    # term exists (0 elsewhere), and dZ/dlambda = -2 lambda (term_c + w_d term_d): the sweep's
+    # lambda and w_d gradients are dL/dZ summed against these per pixel
+    p = GmmParams(Kc=3, Kd=3)
+    rgb, dep, gt = _frames(14, 18, 24)
+    theta = (p.alpha, p.lam, 0.7)
+    Z, has, dc, dd = record_window(rgb, dep, p, theta)
+    assert dd.term.any() and (dc.term & ~dd.term).any()
+    Z64 = replay_window(rgb, dep, p, dc, dd, theta)
+    _, dZ = bce_loss_and_grad(Z64, has, gt)
+    g = reverse_gradient(rgb, dep, p, dc, dd, theta, dZ)
+    slope = (replay_window(rgb, dep, p, dc, dd, (theta[0], theta[1], 1.0)) -
+             replay_window(rgb, dep, p, dc, dd, (theta[0], theta[1], 0.0)))
+    assert np.all(slope[~dd.term] == 0) and np.any(slope[dd.term] != 0)
+    assert np.isclose(g[2], float((dZ * slope).sum()), rtol=1e-10)
+    dZ_dlam = -2.0 * theta[1] * (dc.term + theta[2] * dd.term)
+    assert np.isclose(g[1], float((dZ * dZ_dlam).sum()), rtol=1e-10)
+
+
 def test_loss_matches_torch_bce_with_logits():
     torch = pytest.importorskip("torch")
     rng = np.random.default_rng(0)

@@ -163,6 +163,8 @@ ADJOINT_MUTANTS = [
      "g_alpha += float(np.where(hit, av * (d2n - v[k]), 0.0).sum())", "g_alpha += 0.0"),
     ("mean adjoint without the variance's pull", oracle.adjoint, "_reverse_model",
      "a_mnew = a_mun[k] + av[None] * alpha * (-2.0) * (X - mnew)", "a_mnew = a_mun[k]"),
+    ("depth weight gradient misses lambda squared", oracle.adjoint, "reverse_gradient",
+     "np.where(on_d, del_d - lam2, 0.0)", "np.where(on_d, del_d, 0.0)"),
     ("clamped variance passes its adjoint", oracle.adjoint, "_reverse_model",
      "av = np.where(hit & ~dec.clamp[t], a_vn[k], 0.0)", "av = np.where(hit, a_vn[k], 0.0)"),
 ]
