@@ -365,14 +365,18 @@ def median_mask(mask, radius: int, out=None):
             raise ValueError(f"{name} must be a uint8 [H, W] tensor on the GPU")
         if t.shape[1] > 1 and t.stride(1) != 1:
             raise ValueError(f"{name} rows must be contiguous")
+        if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+            raise ValueError(f"{name} rows must not overlap (row stride {t.stride(0)} < width {t.shape[1]})")
     if out is None:
         out = torch.empty(mask.shape, dtype=torch.uint8, device=mask.device)
     elif tuple(out.shape) != tuple(mask.shape):
         raise ValueError("out must have the mask's shape")
     H, W = mask.shape
+
+    def row_stride(t):   # one row: any stride >= W describes it
+        return t.stride(0) if H > 1 else W
     stream = torch.cuda.current_stream(mask.device).cuda_stream
-    fgs_mask_median(mask.data_ptr(), max(mask.stride(0), W), out.data_ptr(), max(out.stride(0), W), H, W,
-                    radius, stream)
+    fgs_mask_median(mask.data_ptr(), row_stride(mask), out.data_ptr(), row_stride(out), H, W, radius, stream)
     return out
 
 
@@ -534,6 +538,7 @@ class Model:
             g = np.ascontiguousarray(gt, np.uint8)
             fgs_eval_accumulate(self.handle, g.ctypes.data, g.strides[0], FGS_MEM_HOST)
         else:
+            self._check_plane(gt, "gt")
             self._model_waits_for_torch()
             fgs_eval_accumulate(self.handle, gt.data_ptr(), gt.stride(0), FGS_MEM_DEVICE)
             self._torch_waits_for_model()
@@ -542,8 +547,16 @@ class Model:
         """(TP, TN, FP, FN) accumulated since creation or the last reset."""
         return fgs_eval_read(self.handle, reset)
 
+    def _check_plane(self, t, name):
+        """A uint8 [H, W] cuda tensor whose rows are contiguous bytes (rows may be strided)."""
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8 or \
+                tuple(t.shape) != (self.H, self.W) or (self.W > 1 and t.stride(1) != 1):
+            raise ValueError(f"{name} must be a uint8 [{self.H}, {self.W}] cuda tensor with contiguous rows")
+
     def mask_into(self, out) -> None:
         """Device-to-device copy of the latest mask into a uint8 [H, W] cuda tensor."""
+        self._check_plane(out, "out")
         self._model_waits_for_torch()
         fgs_get_mask(self.handle, out.data_ptr(), out.stride(0), FGS_MEM_DEVICE)
         self._torch_waits_for_model()

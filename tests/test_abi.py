@@ -177,3 +177,9 @@ def test_model_push_checks_tensor_arguments():
     for rgb, dep in bad:
         with pytest.raises(ValueError):
             m.push(rgb, dep)
+    # mask read-back and ground truth: uint8 [H, W] cuda tensors with contiguous rows only
+    for t in (torch.zeros(4, 6, dtype=torch.uint8), torch.zeros(6, 4, dtype=torch.uint8).t(), None):
+        with pytest.raises(ValueError):
+            m.mask_into(t)
+        with pytest.raises(ValueError):
+            m.eval_accumulate(t if t is not None else torch.zeros(4, 6, dtype=torch.int16))

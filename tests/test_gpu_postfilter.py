@@ -158,6 +158,13 @@ def test_argument_checks():
         fgs.median_mask(a.float(), 1)
     with pytest.raises(ValueError):
         fgs.median_mask(a, 1, out=torch.zeros((8, 41), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):   # rows broadcast from one: a row stride of 0
+        fgs.median_mask(a[:1].expand(8, 40), 1)
+    # a row-strided view (every other row of a taller buffer) is filtered as laid out
+    tall = torch.from_numpy(_mask(16, 40, 3, "noise")).cuda()
+    got = fgs.median_mask(tall[::2], 2)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle_median(tall[::2].cpu().numpy(), 2))
     # the buffers were never written
     torch.cuda.synchronize()
     assert int(b.sum()) == 0
