@@ -38,13 +38,15 @@ def pbas_bytes_per_px(N=N_PBAS):
     return 4 * N + 2 * (16 + 16 + 8) + 6
 
 
-def kernel_entry(avg_ms, bytes_per_px, gbs, profile, launches_per_step, step_s):
+def kernel_entry(avg_ms, bytes_per_px, gbs, profile, launches_per_step, models_per_launch, step_s):
     """Per-kernel figures of the default benchmark (None if the kernel did not run)."""
     if not launches_per_step:
         return None
-    return {"avg_ms": round(avg_ms, 5), "launches_per_step": launches_per_step, "bytes_per_px": bytes_per_px,
+    return {"avg_ms": round(avg_ms, 5), "launches_per_step": launches_per_step,
+            "models_per_launch": models_per_launch, "bytes_per_px": bytes_per_px,
             "GBs": round(gbs, 1), "traffic": measured_traffic(profile),
-            "Mpx_per_s": round(H * W / (avg_ms * 1e-3) / 1e6, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "Mpx_per_s": round(models_per_launch * H * W / (avg_ms * 1e-3) / 1e6, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4),
             "share_of_step": round(launches_per_step * avg_ms * 1e-3 / step_s, 4)}
 
 
@@ -443,6 +445,8 @@ def main():
     ap.add_argument("--frames", type=int, default=64, help="distinct pre-staged frames (cycled)")
     ap.add_argument("--models", type=lambda v: tuple(int(x) for x in v.split(",")), default=(8, 4),
                     help="GMM,PBAS model counts stepped round-robin (default 8,4: 2.4 GB of live state)")
+    ap.add_argument("--per-model", action="store_true",
+                    help="one launch per model (fgs_push_frame) instead of one per kind (fgs_push_frames)")
     ap.add_argument("--streams", type=int, default=1,
                     help="streams the models are spread over (model j on stream j mod S); with S > 1 "
                          "kernels of different models overlap, and the roofline describes the whole step")
@@ -515,36 +519,53 @@ def main():
         for j, (_, kind) in enumerate(models):
             if kind == "pbas":
                 push(j, i)
-    for i in range(args.warmup):
-        for j in range(len(models)):
-            push(j, N_PBAS + i)
-    torch.cuda.synchronize()
 
-    # A step launches the GMM models, then the PBAS models, back to back on one stream.
-    # Two events per step (its start and the GMM -> PBAS boundary) time each block; a
-    # kernel's average launch is its blocks' total over its launches.  With the models on
-    # several streams the events on the first stream do not bracket the others' work, so
-    # only the wall time of the steps is used.
+    # A step pushes a frame to every GMM model, then to every PBAS model, on one stream:
+    # by default one fgs_push_frames call per kind, i.e. one launch for up to 8 models
+    # (--per-model: one launch each).  Two events per step (its start and the GMM -> PBAS
+    # boundary) time each block; a kernel's average launch is its blocks' total over its
+    # launches.  With the models on several streams the events on the first stream do not
+    # bracket the others' work, so only the wall time of the steps is used.
     K = args.steps
     L = len(models)
+    batched = S == 1 and not args.per_model
+    g_launches = (-(-n_g // 8) if batched else n_g)
+    p_launches = (-(-n_p // 8) if batched else n_p)
+
+    def push_kind(js, i):
+        if not batched:
+            for j in js:
+                push(j, i)
+            return
+        fs = [(i + 7 * j) % F for j in js]
+        fgs.fgs_push_frames([models[j][0].handle for j in js], [rgb[f].data_ptr() for f in fs], [rs] * len(js),
+                            [dep[f].data_ptr() for f in fs], [ds] * len(js))
+    g_js, p_js = list(range(n_g)), list(range(n_g, L))
+    for i in range(args.warmup):
+        for js in (g_js, p_js):
+            if js:
+                push_kind(js, N_PBAS + i)
+    torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K + 1)]
     base = N_PBAS + args.warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(K):
         ev[2 * s].record(stream)
-        for j in range(n_g):
-            push(j, base + s)
+        if g_js:
+            push_kind(g_js, base + s)
         ev[2 * s + 1].record(stream)
-        for j in range(n_g, L):
-            push(j, base + s)
+        if p_js:
+            push_kind(p_js, base + s)
     ev[2 * K].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     g_tot = sum(ev[2 * s].elapsed_time(ev[2 * s + 1]) for s in range(K))
     p_tot = sum(ev[2 * s + 1].elapsed_time(ev[2 * s + 2]) for s in range(K))
-    gmm_ms = g_tot / max(1, K * n_g)
-    pbas_ms = p_tot / max(1, K * n_p)
+    gmm_ms = g_tot / max(1, K * g_launches)
+    pbas_ms = p_tot / max(1, K * p_launches)
+    g_per = n_g / g_launches if g_launches else 0     # models per launch
+    p_per = n_p / p_launches if p_launches else 0
 
     # Untimed: plain streaming copy of the same footprint, to calibrate what a simple
     # kernel reaches on this device.
@@ -566,8 +587,8 @@ def main():
     npx = H * W
     value = L * npx * K / wall / 1e6
     g_b, p_b = gmm_bytes_per_px(), pbas_bytes_per_px()
-    g_gbs = g_b * npx / (gmm_ms * 1e-3) / 1e9 if n_g else 0.0
-    p_gbs = p_b * npx / (pbas_ms * 1e-3) / 1e9 if n_p else 0.0
+    g_gbs = g_per * g_b * npx / (gmm_ms * 1e-3) / 1e9 if n_g else 0.0
+    p_gbs = p_per * p_b * npx / (pbas_ms * 1e-3) / 1e9 if n_p else 0.0
     if S > 1:
         # kernels of different models overlap: the roofline describes a whole step (all
         # models' algorithmic bytes over the step's wall time); traffic adds the profiled
@@ -597,7 +618,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     # dominant kernel: the larger share of a step's time
-    dom = "pbas" if n_p * pbas_ms >= n_g * gmm_ms else "gmm"
+    dom = "pbas" if p_launches * pbas_ms >= g_launches * gmm_ms else "gmm"
     ach = p_gbs if dom == "pbas" else g_gbs
     out = {
         "metric": "Mpixel-frames/s (GMM K=5 + PBAS N=35 RGB-D steps) and HBM roofline fraction",
@@ -612,18 +633,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"RGB-D 1280x720, {n_g} GMM Kc=Kd=5 + {n_p} PBAS N=35 independent models "
-                               "stepped round-robin, 8 moving objects + shadows",
+        "config": {"workload": f"RGB-D 1280x720, {n_g} GMM Kc=Kd=5 + {n_p} PBAS N=35 independent models, "
+                               + ("one launch per kind and step" if batched else "one launch per model and step")
+                               + ", 8 moving objects + shadows",
                    "H": H, "W": W, "gmm_K": KC, "pbas_N": N_PBAS, "gmm_models": n_g, "pbas_models": n_p,
                    "live_state_bytes": live, "frames_cycled": F, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic("pbas_step_1280x720_n35.txt" if dom == "pbas"
                                                  else "gmm_step_1280x720_k5.txt"),
-                     "kernel": dom + "_step", "algorithmic_bytes_per_launch": (p_b if dom == "pbas" else g_b) * npx},
+                     "kernel": dom + "_step",
+                     "algorithmic_bytes_per_launch": int(p_per * p_b * npx if dom == "pbas" else g_per * g_b * npx)},
         "kernels": {k: v for k, v in (
-            ("gmm_step", kernel_entry(gmm_ms, g_b, g_gbs, "gmm_step_1280x720_k5.txt", n_g, wall / K)),
-            ("pbas_step", kernel_entry(pbas_ms, p_b, p_gbs, "pbas_step_1280x720_n35.txt", n_p, wall / K)))
+            ("gmm_step", kernel_entry(gmm_ms, g_b, g_gbs, "gmm_step_1280x720_k5.txt", g_launches, g_per, wall / K)),
+            ("pbas_step", kernel_entry(pbas_ms, p_b, p_gbs, "pbas_step_1280x720_n35.txt", p_launches, p_per,
+                                       wall / K)))
             if v is not None},
         "copy_probe_GBs": round(copy_gbs, 1),
     }

@@ -208,6 +208,29 @@ fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_s
                                  int32_t depth_W, fgs_mem where);
 
 /*
+ * Push one frame to each of n independent models (many cameras) with as few
+ * launches as possible: the result is exactly that of fgs_push_frame(models[i],
+ * rgb[i], rgb_stride[i], depth[i], depth_stride[i], FGS_MEM_DEVICE) for each i.
+ * Models of one kind and class share a launch of up to 8 models (GMM: same Kc,
+ * Kd, variant and cache policy; PBAS: past its N fill frames, same register class
+ * of N and cache policy), so the device ramps up and drains once per launch
+ * instead of once per model; other models get launches of their own.
+ *
+ * Frames are device memory, each of its model's H x W size (no depth
+ * upscaling), rows rgb_stride[i] >= 3W and depth_stride[i] >= 2W (even) bytes
+ * apart, read in stream order as by fgs_push_frame.  Every model must have been
+ * created on the same stream and device, and appear once.  1 <= n <= 4096.
+ * Errors: INVALID_ARG for NULL arrays or entries, bad strides, mixed streams or
+ * devices, a repeated model or n out of range; BAD_STATE for an exhausted frame
+ * counter; DEVICE for a poisoned model.  These are checked for every model first,
+ * and then no model takes its frame.  A failing launch poisons the models it
+ * held (DEVICE).
+ */
+fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* const* rgb,
+                           const int64_t* rgb_stride, const uint16_t* const* depth,
+                           const int64_t* depth_stride);
+
+/*
  * Copy the mask of the most recent frame into `mask` (H rows of W bytes,
  * `stride` bytes apart; 255 = foreground, 0 = background).  FGS_MEM_HOST waits
  * for the frame to finish; FGS_MEM_DEVICE enqueues a device copy on the model's

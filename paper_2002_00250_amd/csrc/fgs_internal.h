@@ -10,6 +10,13 @@
 
 namespace fgs {
 
+// ------------------------------------------------------------- batches ----
+// Up to kBatchMax models of one kind and class stepped by one launch (their
+// arguments travel by value): workgroup w belongs to model i when
+// first[i] <= w < first[i + 1], first[0] = 0, first[n] = the grid size.  One launch
+// over many independent models has one ramp-up and one drain instead of one each.
+constexpr int kBatchMax = 8;
+
 // ---------------------------------------------------------------- GMM ----
 // Device layout: per pixel, Kc "core" float4 planes (mu_r, mu_g, mu_b, v) of the
 // colour Gaussians by rank, then E "extra" float4 planes holding, in order, the
@@ -51,9 +58,19 @@ struct GmmStepArgs {
     GmmConsts c;
 };
 
+struct GmmBatch {
+    int32_t n;
+    int32_t first[kBatchMax + 1];
+    GmmStepArgs a[kBatchMax];
+};
+
 hipError_t gmm_launch_init(float4* state, int Kc, int Kd, int npix, const GmmConsts& c,
                            hipStream_t s);
 hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s);
+// One launch over n <= kBatchMax models with the same Kc, Kd, cache policy and
+// kernel variant (gmm_batch_key equal).
+hipError_t gmm_launch_step_batch(const GmmStepArgs* a, int n, int Kc, int Kd, hipStream_t s);
+int gmm_batch_key(const GmmStepArgs& a, int Kc, int Kd);
 // canonical planar float32 <-> device layout
 hipError_t gmm_launch_export(const float4* state, float* out, int Kc, int Kd, int var_mode, int npix,
                              hipStream_t s);
@@ -129,7 +146,18 @@ struct PbasStepArgs {
 
 hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConsts& c,
                                   hipStream_t s);
+struct PbasBatch {
+    int32_t n;
+    int32_t first[kBatchMax + 1];
+    int32_t tiles_x[kBatchMax];
+    PbasStepArgs a[kBatchMax];
+};
+
 hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s);
+// One launch over n <= kBatchMax models past their fill frames with the same
+// register class and cache policy (pbas_batch_key equal, not -1).
+hipError_t pbas_launch_step_batch(const PbasStepArgs* a, int n, hipStream_t s);
+int pbas_batch_key(const PbasStepArgs& a);  // -1: a fill frame (its own launch)
 hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, const PbasConsts& c,
                              hipStream_t s);
 hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out, hipStream_t s);

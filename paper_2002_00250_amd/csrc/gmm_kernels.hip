@@ -16,6 +16,8 @@
 //     q_k < lambda^2 matches; w = (1-alpha) w (+ alpha if matched); matched
 //     mu += alpha (X - mu); v += alpha (|X - mu_new|^2 - v); v >= v_min; no match:
 //     Gaussian K-1 = (w_init, X, v_init); w /= sum(w); stable sort by w/sqrt(v).
+#include <cstring>
+
 #include "device_common.h"
 #include "fgs_internal.h"
 #include "gmm_device.h"
@@ -28,9 +30,16 @@ constexpr int kBlock = 256;
 
 // GEN = false: the default rate and decision compiled in; GEN = true: both read
 // from the constants (any other choice).  CV = 3: per-channel colour variances.
+// One launch steps b.n models (one for a single push): workgroup w takes pixels
+// 256 (w - first[i]) .. +255 of model i, first[i] <= w < first[i + 1].
 template <int KC, int KD, bool NT, bool GEN, int CV>
-__global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmStepArgs a) {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmBatch b) {
+    const int w = (int)blockIdx.x;
+    int i = 0;
+#pragma unroll
+    for (int j = 1; j < kBatchMax; ++j) i += (j < b.n && w >= b.first[j]) ? 1 : 0;
+    const GmmStepArgs& a = b.a[i];
+    const int p = (w - b.first[i]) * kBlock + (int)threadIdx.x;
     if (p < a.npix) gmm_pixel<KC, KD, NT, GEN ? 2 : 0, GEN ? 2 : 0, CV>(a, p);
 }
 
@@ -122,19 +131,24 @@ __global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd
 }
 
 template <int KC, int KD, bool GEN, int CV>
-void launch_step_g(const GmmStepArgs& a, unsigned grid, hipStream_t s) {
-    if (a.streaming)
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, a);
+void launch_step_g(const GmmBatch& b, unsigned grid, hipStream_t s) {
+    if (b.a[0].streaming)
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, b);
     else
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, b);
 }
 
+// Kernel variant of a model's constants: 2 per-channel variances, 1 rate or decision
+// variant, 0 the defaults compiled in.
+int variant(const GmmConsts& c) { return c.var_mode ? 2 : ((c.rho_mode || c.decision) ? 1 : 0); }
+
 template <int KC, int KD>
-hipError_t launch_step_t(const GmmStepArgs& a, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.npix + kBlock - 1) / kBlock);
-    if (a.c.var_mode) launch_step_g<KC, KD, true, 3>(a, grid, s);
-    else if (a.c.rho_mode || a.c.decision) launch_step_g<KC, KD, true, 1>(a, grid, s);
-    else launch_step_g<KC, KD, false, 1>(a, grid, s);
+hipError_t launch_step_t(const GmmBatch& b, unsigned grid, hipStream_t s) {
+    switch (variant(b.a[0].c)) {
+        case 2: launch_step_g<KC, KD, true, 3>(b, grid, s); break;
+        case 1: launch_step_g<KC, KD, true, 1>(b, grid, s); break;
+        default: launch_step_g<KC, KD, false, 1>(b, grid, s); break;
+    }
     return hipGetLastError();
 }
 
@@ -145,18 +159,40 @@ bool gmm_supported(int Kc, int Kd) {
     return Kc == 7 && Kd == 3;
 }
 
-hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s) {
+int gmm_batch_key(const GmmStepArgs& a, int Kc, int Kd) {
+    return ((Kc * 8 + Kd) * 4 + variant(a.c)) * 2 + (a.streaming ? 1 : 0);
+}
+
+hipError_t gmm_launch_step_batch(const GmmStepArgs* a, int n, int Kc, int Kd, hipStream_t s) {
+    if (n < 1 || n > kBatchMax) return hipErrorInvalidValue;
+    GmmBatch b;
+    std::memset(&b, 0, sizeof b);
+    b.n = n;
+    int64_t grid = 0;
+    for (int i = 0; i < n; ++i) {
+        if (gmm_batch_key(a[i], Kc, Kd) != gmm_batch_key(a[0], Kc, Kd)) return hipErrorInvalidValue;
+        b.a[i] = a[i];
+        b.first[i] = (int32_t)grid;
+        grid += (a[i].npix + kBlock - 1) / kBlock;
+    }
+    for (int i = n; i <= kBatchMax; ++i) b.first[i] = (int32_t)grid;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)grid;
     switch (Kc * 8 + Kd) {
-        case 1 * 8 + 1: return launch_step_t<1, 1>(a, s);
-        case 2 * 8 + 2: return launch_step_t<2, 2>(a, s);
-        case 3 * 8 + 3: return launch_step_t<3, 3>(a, s);
-        case 4 * 8 + 4: return launch_step_t<4, 4>(a, s);
-        case 5 * 8 + 5: return launch_step_t<5, 5>(a, s);
-        case 6 * 8 + 6: return launch_step_t<6, 6>(a, s);
-        case 7 * 8 + 7: return launch_step_t<7, 7>(a, s);
-        case 7 * 8 + 3: return launch_step_t<7, 3>(a, s);
+        case 1 * 8 + 1: return launch_step_t<1, 1>(b, g, s);
+        case 2 * 8 + 2: return launch_step_t<2, 2>(b, g, s);
+        case 3 * 8 + 3: return launch_step_t<3, 3>(b, g, s);
+        case 4 * 8 + 4: return launch_step_t<4, 4>(b, g, s);
+        case 5 * 8 + 5: return launch_step_t<5, 5>(b, g, s);
+        case 6 * 8 + 6: return launch_step_t<6, 6>(b, g, s);
+        case 7 * 8 + 7: return launch_step_t<7, 7>(b, g, s);
+        case 7 * 8 + 3: return launch_step_t<7, 3>(b, g, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s) {
+    return gmm_launch_step_batch(&a, 1, Kc, Kd, s);
 }
 
 hipError_t gmm_launch_init(float4* state, int Kc, int Kd, int npix, const GmmConsts& c,

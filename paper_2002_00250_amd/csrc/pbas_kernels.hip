@@ -2,6 +2,8 @@
 // (fill for the first N frames, then the tile update of pbas_device.h), the
 // flush of pending neighbour writes before a state read-out, and the state
 // import/export.
+#include <cstring>
+
 #include "device_common.h"
 #include "fgs_internal.h"
 #include "pbas_device.h"
@@ -21,14 +23,19 @@ __global__ __launch_bounds__(256) void pbas_fill_kernel(PbasStepArgs a) {
 // Register capacity class NMAX serves N in [class_min(NMAX), NMAX].
 constexpr int class_min(int nmax) { return nmax <= 8 ? 2 : (nmax <= 40 ? nmax - 3 : nmax - 7); }
 
-// One block per 64x4 tile on a one-dimensional grid (row-major tile order): the
-// grid's y extent is too small for the tile rows of a tall image.
+// One block per 64x4 tile on a one-dimensional grid (row-major tile order within a
+// model): the grid's y extent is too small for the tile rows of a tall image.  One
+// launch steps b.n models (one for a single push): workgroup w takes tile
+// w - first[i] of model i, first[i] <= w < first[i + 1].
 template <int NMAX, bool NT>
-__global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasStepArgs a) {
+__global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasBatch b) {
     __shared__ PbasLds<NMAX> sh;
-    const int tiles_x = (a.W + kTileW - 1) / kTileW;
-    const int b = (int)blockIdx.x;
-    pbas_tile<NMAX, class_min(NMAX), NT>(a, b % tiles_x, b / tiles_x, sh);
+    const int w = (int)blockIdx.x;
+    int i = 0;
+#pragma unroll
+    for (int j = 1; j < kBatchMax; ++j) i += (j < b.n && w >= b.first[j]) ? 1 : 0;
+    const int local = w - b.first[i], tiles_x = b.tiles_x[i];
+    pbas_tile<NMAX, class_min(NMAX), NT>(b.a[i], local % tiles_x, local / tiles_x, sh);
 }
 
 // Apply the neighbour writes of the last processed frame (read-out of the logical
@@ -122,27 +129,36 @@ __global__ void pbas_import_samples_kernel(uint4* quads, const uint32_t* in, int
 inline unsigned blocks1d(int n) { return (unsigned)((n + 255) / 256); }
 
 template <int NMAX>
-void launch_step_nt(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
-    if (a.streaming) hipLaunchKernelGGL((pbas_step_kernel<NMAX, true>), grid, dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((pbas_step_kernel<NMAX, false>), grid, dim3(kBlock), 0, s, a);
+void launch_step_nt(const PbasBatch& b, dim3 grid, hipStream_t s) {
+    if (b.a[0].streaming) hipLaunchKernelGGL((pbas_step_kernel<NMAX, true>), grid, dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL((pbas_step_kernel<NMAX, false>), grid, dim3(kBlock), 0, s, b);
 }
 
 // Register capacity for the N sample words: the smallest instantiated NMAX >= N
 // (multiples of 4 up to 40, then 48, 56, 64), so that N >= class_min(NMAX).
-void launch_step_n(const PbasStepArgs& a, dim3 grid, hipStream_t s) {
-    switch ((a.c.N + 3) / 4) {
-        case 0: case 1: case 2: launch_step_nt<8>(a, grid, s); break;
-        case 3: launch_step_nt<12>(a, grid, s); break;
-        case 4: launch_step_nt<16>(a, grid, s); break;
-        case 5: launch_step_nt<20>(a, grid, s); break;
-        case 6: launch_step_nt<24>(a, grid, s); break;
-        case 7: launch_step_nt<28>(a, grid, s); break;
-        case 8: launch_step_nt<32>(a, grid, s); break;
-        case 9: launch_step_nt<36>(a, grid, s); break;
-        case 10: launch_step_nt<40>(a, grid, s); break;
-        case 11: case 12: launch_step_nt<48>(a, grid, s); break;
-        case 13: case 14: launch_step_nt<56>(a, grid, s); break;
-        default: launch_step_nt<64>(a, grid, s); break;
+int nmax_class(int N) {
+    switch ((N + 3) / 4) {
+        case 0: case 1: case 2: return 8;
+        case 11: case 12: return 48;
+        case 13: case 14: return 56;
+        default: return (N + 3) / 4 <= 10 ? 4 * ((N + 3) / 4) : 64;
+    }
+}
+
+void launch_step_n(const PbasBatch& b, dim3 grid, hipStream_t s) {
+    switch (nmax_class(b.a[0].c.N)) {
+        case 8: launch_step_nt<8>(b, grid, s); break;
+        case 12: launch_step_nt<12>(b, grid, s); break;
+        case 16: launch_step_nt<16>(b, grid, s); break;
+        case 20: launch_step_nt<20>(b, grid, s); break;
+        case 24: launch_step_nt<24>(b, grid, s); break;
+        case 28: launch_step_nt<28>(b, grid, s); break;
+        case 32: launch_step_nt<32>(b, grid, s); break;
+        case 36: launch_step_nt<36>(b, grid, s); break;
+        case 40: launch_step_nt<40>(b, grid, s); break;
+        case 48: launch_step_nt<48>(b, grid, s); break;
+        case 56: launch_step_nt<56>(b, grid, s); break;
+        default: launch_step_nt<64>(b, grid, s); break;
     }
 }
 
@@ -156,15 +172,39 @@ hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConst
     return hipGetLastError();
 }
 
-hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
-    if ((int)a.t < a.c.N) {
-        hipLaunchKernelGGL(pbas_fill_kernel, dim3(blocks1d(a.npix)), dim3(256), 0, s, a);
-    } else {
+int pbas_batch_key(const PbasStepArgs& a) {
+    if ((int)a.t < a.c.N) return -1;
+    return nmax_class(a.c.N) * 2 + (a.streaming ? 1 : 0);
+}
+
+hipError_t pbas_launch_step_batch(const PbasStepArgs* a, int n, hipStream_t s) {
+    if (n < 1 || n > kBatchMax) return hipErrorInvalidValue;
+    PbasBatch b;
+    std::memset(&b, 0, sizeof b);
+    b.n = n;
+    int64_t grid = 0;
+    for (int i = 0; i < n; ++i) {
+        const int key = pbas_batch_key(a[i]);
+        if (key < 0 || key != pbas_batch_key(a[0])) return hipErrorInvalidValue;
+        b.a[i] = a[i];
+        b.tiles_x[i] = (a[i].W + kTileW - 1) / kTileW;
+        b.first[i] = (int32_t)grid;
         // ceil(W/64) * ceil(H/4) <= H*W/256 + W/64 + H/4 + 1 < 2^27 tiles for H*W <= 2^28
-        const int64_t tiles = (int64_t)((a.W + kTileW - 1) / kTileW) * ((a.H + kTileH - 1) / kTileH);
-        launch_step_n(a, dim3((unsigned)tiles), s);
+        grid += (int64_t)b.tiles_x[i] * ((a[i].H + kTileH - 1) / kTileH);
     }
+    for (int i = n; i <= kBatchMax; ++i) b.first[i] = (int32_t)grid;
+    for (int i = n; i < kBatchMax; ++i) b.tiles_x[i] = 1;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    launch_step_n(b, dim3((unsigned)grid), s);
     return hipGetLastError();
+}
+
+hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
+    if (pbas_batch_key(a) < 0) {
+        hipLaunchKernelGGL(pbas_fill_kernel, dim3(blocks1d(a.npix)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    return pbas_launch_step_batch(&a, 1, s);
 }
 
 hipError_t pbas_launch_flush(const PbasPlanes& m, int H, int W, uint32_t t_prev, const PbasConsts& c,

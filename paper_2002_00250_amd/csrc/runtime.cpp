@@ -511,6 +511,75 @@ fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_s
     return FGS_OK;
 }
 
+fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* const* rgb,
+                           const int64_t* rgb_stride, const uint16_t* const* depth,
+                           const int64_t* depth_stride) {
+    if (n < 1 || n > 4096) return fail(FGS_ERR_INVALID_ARG, "push_frames: n = %d outside 1..4096", n);
+    if (!models || !rgb || !rgb_stride || !depth || !depth_stride)
+        return fail(FGS_ERR_INVALID_ARG, "push_frames: NULL array");
+    // every check first: either every model takes its frame or none does
+    for (int i = 0; i < n; ++i) {
+        fgs_model* m = models[i];
+        if (!m) return fail(FGS_ERR_INVALID_ARG, "push_frames: model %d is NULL", i);
+        if (m->poisoned) return fail(FGS_ERR_DEVICE, "push_frames: model %d is poisoned by an earlier device error", i);
+        if (!rgb[i] || !depth[i]) return fail(FGS_ERR_INVALID_ARG, "push_frames: frame %d is NULL", i);
+        if (rgb_stride[i] < 3 * (int64_t)m->W || depth_stride[i] < 2 * (int64_t)m->W || (depth_stride[i] & 1) ||
+            ((uintptr_t)depth[i] & 1))
+            return fail(FGS_ERR_INVALID_ARG, "push_frames: bad stride (rgb %lld, depth %lld) for model %d, W = %d",
+                        (long long)rgb_stride[i], (long long)depth_stride[i], i, m->W);
+        if (m->t >= 0xFFFFFFFFll) return fail(FGS_ERR_BAD_STATE, "push_frames: model %d frame counter exhausted", i);
+        if (m->stream != models[0]->stream || m->device != models[0]->device)
+            return fail(FGS_ERR_INVALID_ARG, "push_frames: model %d has another stream or device than model 0", i);
+        for (int j = 0; j < i; ++j)
+            if (models[j] == m) return fail(FGS_ERR_INVALID_ARG, "push_frames: model %d appears twice", i);
+    }
+    hipStream_t s = models[0]->stream;
+    std::vector<GmmStepArgs> ga(n);
+    std::vector<PbasStepArgs> pa(n);
+    std::vector<int> key(n), done(n, 0);
+    for (int i = 0; i < n; ++i) {
+        fgs_model* m = models[i];
+        const uint8_t* d = reinterpret_cast<const uint8_t*>(depth[i]);
+        if (m->algo == FGS_GMM) {
+            model_next_gmm(m, rgb[i], rgb_stride[i], d, depth_stride[i], 0, 0, &ga[i]);
+            key[i] = gmm_batch_key(ga[i], m->gp.Kc, m->gp.Kd);
+        } else {
+            model_next_pbas(m, rgb[i], rgb_stride[i], d, depth_stride[i], 0, 0, &pa[i]);
+            key[i] = pbas_batch_key(pa[i]);
+        }
+    }
+    // models of one kind and key share a launch (up to kBatchMax each); fill frames go alone
+    auto fail_group = [&](const std::vector<int>& idx, hipError_t e) {
+        for (int k : idx) (void)device_fail(models[k], e, "push_frames");
+        return device_fail(models[idx[0]], e, "push_frames");
+    };
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        fgs_model* m = models[i];
+        std::vector<int> idx;
+        for (int j = i; j < n && (int)idx.size() < kBatchMax; ++j)
+            if (!done[j] && models[j]->algo == m->algo && key[j] == key[i] &&
+                (m->algo == FGS_PBAS || (models[j]->gp.Kc == m->gp.Kc && models[j]->gp.Kd == m->gp.Kd)) &&
+                (key[i] >= 0 || j == i))
+                idx.push_back(j);
+        for (int k : idx) done[k] = 1;
+        hipError_t e;
+        if (m->algo == FGS_GMM) {
+            GmmStepArgs b[kBatchMax];
+            for (size_t k = 0; k < idx.size(); ++k) b[k] = ga[idx[k]];
+            e = gmm_launch_step_batch(b, (int)idx.size(), m->gp.Kc, m->gp.Kd, s);
+        } else if (key[i] < 0) {
+            e = pbas_launch_step(pa[i], s);
+        } else {
+            PbasStepArgs b[kBatchMax];
+            for (size_t k = 0; k < idx.size(); ++k) b[k] = pa[idx[k]];
+            e = pbas_launch_step_batch(b, (int)idx.size(), s);
+        }
+        if (e != hipSuccess) return fail_group(idx, e);
+    }
+    return FGS_OK;
+}
+
 fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem where) {
     if (!m || !mask) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
     if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");

@@ -95,6 +95,8 @@ def _load():
         "fgs_destroy": (S, [c_void_p]),
         "fgs_push_frame": (S, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32]),
         "fgs_push_frame_scaled": (S, [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32, c_int32]),
+        "fgs_push_frames": (S, [POINTER(c_void_p), c_int32, POINTER(c_void_p), POINTER(c_int64),
+                                POINTER(c_void_p), POINTER(c_int64)]),
         "fgs_get_mask": (S, [c_void_p, c_void_p, c_int64, c_int32]),
         "fgs_mask_device_ptr": (S, [c_void_p, POINTER(c_void_p)]),
         "fgs_eval_accumulate": (S, [c_void_p, c_void_p, c_int64, c_int32]),
@@ -190,6 +192,31 @@ def fgs_push_frame_scaled(m: int, rgb: int, rgb_stride: int, depth: int, depth_s
                           depth_W: int, where: int) -> None:
     _check(_load().fgs_push_frame_scaled(c_void_p(m), c_void_p(rgb), rgb_stride, c_void_p(depth),
                                          depth_stride, depth_H, depth_W, where))
+
+
+def fgs_push_frames(models, rgb, rgb_stride, depth, depth_stride) -> None:
+    """Raw call: sequences of model handles, device frame addresses and row strides."""
+    n = len(models)
+    ptrs = lambda xs: (c_void_p * n)(*[c_void_p(x) for x in xs])
+    i64 = lambda xs: (c_int64 * n)(*xs)
+    _check(_load().fgs_push_frames(ptrs(models), n, ptrs(rgb), i64(rgb_stride), ptrs(depth), i64(depth_stride)))
+
+
+def push_frames(models, rgbs, depths) -> None:
+    """One device frame to each of several Models created on the same stream (uint8
+    [H, W, 3] and 16-bit [H, W] cuda tensors, each of its model's size), in as few
+    launches as the models' kinds and classes allow; the same results as pushing each."""
+    if not models:
+        return
+    if not (len(models) == len(rgbs) == len(depths)):
+        raise ValueError("models, rgbs and depths differ in length")
+    for m, r, d in zip(models, rgbs, depths):
+        m._check_frame(r, d)
+    m0 = models[0]
+    m0._model_waits_for_torch()
+    fgs_push_frames([m.handle for m in models], [r.data_ptr() for r in rgbs], [r.stride(0) for r in rgbs],
+                    [d.data_ptr() for d in depths], [2 * d.stride(0) for d in depths])
+    m0._torch_waits_for_model()
 
 
 def fgs_get_mask(m: int, mask: int, stride: int, where: int) -> None:
@@ -493,19 +520,32 @@ class Model:
             return x.ctypes.data, FGS_MEM_HOST
         return x.data_ptr(), (FGS_MEM_DEVICE if x.is_cuda else FGS_MEM_HOST)
 
+    def _check_tensors(self, rgb, depth):
+        torch = self._torch
+        if rgb.dtype != torch.uint8 or rgb.dim() != 3 or rgb.shape[2] != 3 or \
+                rgb.stride(2) != 1 or rgb.stride(1) != 3:
+            raise ValueError("rgb must be uint8 [H, W, 3] with packed pixels (rows may be strided)")
+        if depth.dtype not in (torch.int16, getattr(torch, "uint16", torch.int16)) or \
+                depth.dim() != 2 or depth.stride(1) != 1:
+            raise ValueError("depth must be 16-bit [H, W] with packed pixels (rows may be strided)")
+
+    def _check_frame(self, rgb, depth):
+        """A device frame of this model's size, for push_frames."""
+        torch = self._torch
+        if not isinstance(rgb, torch.Tensor) or not isinstance(depth, torch.Tensor) or \
+                not rgb.is_cuda or not depth.is_cuda:
+            raise ValueError("push_frames takes cuda tensors")
+        self._check_tensors(rgb, depth)
+        if tuple(rgb.shape[:2]) != (self.H, self.W) or tuple(depth.shape) != (self.H, self.W):
+            raise ValueError(f"frames must be {(self.H, self.W)} for this model")
+
     def push(self, rgb, depth):
         """Push one frame; a depth map of another size than rgb is upscaled to it."""
         if isinstance(rgb, np.ndarray):
             rgb = np.ascontiguousarray(rgb, np.uint8)
             depth = np.ascontiguousarray(depth, np.uint16)
         else:
-            torch = self._torch
-            if rgb.dtype != torch.uint8 or rgb.dim() != 3 or rgb.shape[2] != 3 or \
-                    rgb.stride(2) != 1 or rgb.stride(1) != 3:
-                raise ValueError("rgb must be uint8 [H, W, 3] with packed pixels (rows may be strided)")
-            if depth.dtype not in (torch.int16, getattr(torch, "uint16", torch.int16)) or \
-                    depth.dim() != 2 or depth.stride(1) != 1:
-                raise ValueError("depth must be 16-bit [H, W] with packed pixels (rows may be strided)")
+            self._check_tensors(rgb, depth)
         if tuple(rgb.shape[:2]) != (self.H, self.W):
             raise ValueError(f"rgb is {tuple(rgb.shape[:2])}, the model is {(self.H, self.W)}")
         pr, wr = self._ptr_where(rgb)

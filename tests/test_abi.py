@@ -73,6 +73,12 @@ def test_errors_without_device(libfgs):
         assert e.value.status == fgs.FGS_ERR_INVALID_ARG, args
     fgs.fgs_mask_median(0, 0, 0, 0, 0, 7, 3)
     fgs.fgs_mask_median(0, 0, 0, 0, 7, 0, 3)
+    # batched pushes: an empty batch and a NULL model are refused before any device work
+    for models in ([], [0], [0, 0]):
+        n = len(models)
+        with pytest.raises(fgs.FgsError) as e:
+            fgs.fgs_push_frames(models, [16] * n, [96] * n, [16] * n, [64] * n)
+        assert e.value.status == fgs.FGS_ERR_INVALID_ARG, models
     with pytest.raises(fgs.FgsError) as e:
         fgs.fgs_create(fgs.FGS_GMM, 0, 10)
     assert e.value.status == fgs.FGS_ERR_INVALID_ARG
