@@ -224,7 +224,7 @@ fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_s
  * devices, a repeated model or n out of range; BAD_STATE for an exhausted frame
  * counter; DEVICE for a poisoned model.  These are checked for every model first,
  * and then no model takes its frame.  A failing launch poisons the models it
- * held (DEVICE).
+ * held and those whose launch had not been issued yet (DEVICE).
  */
 fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* const* rgb,
                            const int64_t* rgb_stride, const uint16_t* const* depth,

@@ -548,9 +548,13 @@ fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* c
             key[i] = pbas_batch_key(pa[i]);
         }
     }
-    // models of one kind and key share a launch (up to kBatchMax each); fill frames go alone
+    // models of one kind and key share a launch (up to kBatchMax each); fill frames go alone.
+    // Every frame counter has advanced: a failed launch poisons its models and every model
+    // whose launch had not been issued yet.
     auto fail_group = [&](const std::vector<int>& idx, hipError_t e) {
-        for (int k : idx) (void)device_fail(models[k], e, "push_frames");
+        for (int k : idx) models[k]->poisoned = true;
+        for (int k = 0; k < n; ++k)
+            if (!done[k]) models[k]->poisoned = true;
         return device_fail(models[idx[0]], e, "push_frames");
     };
     for (int i = 0; i < n; ++i) {
