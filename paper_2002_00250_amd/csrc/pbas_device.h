@@ -309,6 +309,13 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     const uint32_t keep = (lastw >> 24) != 0u ? 0xFFFFFFFFu : 0x00FFFFFFu;  // depth at t-1?
 #pragma unroll
     for (int w = 0; w < NW; ++w) pw[w] = a.apply_pending ? sh.pend[w * kBlock + tid] & keep : 0u;
+    // Quad q of the samples can change only where a pending or self-update bit of one
+    // of its slots is set (nibble q & 1 of every byte of bit-word q >> 1) or where it
+    // holds the previous-value slot; bit q of `dirty`.
+    uint32_t dirty = 0u;
+#pragma unroll
+    for (int q = 0; q < NMAX / 4; ++q)
+        dirty |= ((pw[q >> 1] & ((q & 1) ? 0xF0F0F0F0u : 0x0F0F0F0Fu)) != 0u ? 1u : 0u) << q;
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         // Keep the per-slot work next to its sample: without the fence the scheduler
@@ -360,6 +367,9 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             const uint32_t bm = slot_byte_mask(sw[k >> 3], k);
             sm[k] = (sm[k] & ~bm) | (Iw & bm);
         }
+#pragma unroll
+        for (int q = 0; q < NMAX / 4; ++q)
+            dirty |= ((sw[q >> 1] & ((q & 1) ? 0xF0F0F0F0u : 0x0F0F0F0Fu)) != 0u ? 1u : 0u) << q;
     }
     // A D-history byte is written only when it changes: on a static background d_min is
     // mostly 0 or 1 and often equals the byte it replaces, and each write that is left
@@ -407,12 +417,23 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 #pragma unroll
         for (int k = NLO; k < NMAX; ++k)
             if (k == N) sm[k] = Iw;
+        dirty |= 1u << (N >> 2);
+    }
+    // A 64-byte sector of a quad plane holds 4 consecutive pixels (lanes 4i..4i+3 of a
+    // tile row): a quad's store is left out only where it changed in none of the 4, so
+    // every write still covers whole sectors.  Lanes past the image edge have left and
+    // can only add bits (a store too many, never one too few).
+    // (Up to 40 slots: for more, the bits' registers would cost occupancy.)
+    constexpr bool kSkipClean = NMAX <= 40;
+    if (kSkipClean) {
+        dirty |= __shfl_xor(dirty, 1, 64);
+        dirty |= __shfl_xor(dirty, 2, 64);
     }
     uint32_t* sbase = a.m.samples + p0 * 4;
     asm volatile("" : "+s"(sbase));
 #pragma unroll
     for (int q = 0; q < NMAX / 4; ++q)
-        if (4 * q < NLO || 4 * q < N) {
+        if ((4 * q < NLO || 4 * q < N) && (!kSkipClean || ((dirty >> q) & 1u))) {
             const u32x4 v = {sm[4 * q], sm[4 * q + 1], sm[4 * q + 2], sm[4 * q + 3]};
             st_quad<NT>(sbase, npix, qrange, q, voff, v);
         }
