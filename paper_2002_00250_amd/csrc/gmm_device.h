@@ -305,8 +305,16 @@ __device__ __forceinline__ float density_factor(float delta, float v, float s) {
 // the matched mean and variance: 0 alpha, 1 as a.c.rho_mode says;
 // DEC the decision: 0 the Z rule, 1 the density product, 2 as a.c.decision says
 // (a compile-time choice keeps the other path's registers out of the kernel).
-// A plane is stored only when some lane of the wavefront may have changed it
-// (the skip is wavefront-uniform, so every store still covers whole lines).
+// A plane is stored only where one of the 4 pixels sharing the lane's 64-byte
+// sector of it (lanes 4i..4i+3: 16 bytes per pixel) may have changed it, so every
+// store still covers whole sectors.
+__device__ __forceinline__ bool sector_any(bool b) {
+    uint32_t v = b ? 1u : 0u;
+    v |= __shfl_xor(v, 1, 64);
+    v |= __shfl_xor(v, 2, 64);
+    return v != 0u;
+}
+
 template <int KC, int KD, bool NT, int RW = 2, int DEC = 2, int CV = 1>
 __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     using L = GmmLayout<KC, KD, CV>;
@@ -374,7 +382,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     // the colour means and variances are final: store them before the depth step
 #pragma unroll
     for (int k = 0; k < KC; ++k)
-        if (__any((chg_c >> k) & 1u))
+        if (sector_any((chg_c >> k) & 1u))
             st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.mu[k][0], mc.mu[k][1], mc.mu[k][2], mc.v[k]));
     mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
                                a.c.v_min_d, used_d, dd, nullptr, rw, &chg_d, DEC ? &vsel_d : nullptr);
@@ -422,7 +430,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
             else if (i < KC + 3 * KD) ch = ch || ((chg_d >> ((i - KC - KD) >> 1)) & 1u);
             else if (i < L::NX) ch = ch || ((chg_c >> ((i - KC - 3 * KD) >> 1)) & 1u);
         }
-        if (__any(ch))
+        if (sector_any(ch))
             st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,
                          make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]));
     }
