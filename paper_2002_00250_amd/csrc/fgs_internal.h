@@ -58,10 +58,13 @@ struct GmmStepArgs {
     GmmConsts c;
 };
 
+// Capacity NB: a single push uses NB = 1 (small kernel arguments, one launch's
+// latency as before batching), batches of 2..kBatchMax use NB = kBatchMax.
+template <int NB>
 struct GmmBatch {
     int32_t n;
-    int32_t first[kBatchMax + 1];
-    GmmStepArgs a[kBatchMax];
+    int32_t first[NB + 1];
+    GmmStepArgs a[NB];
 };
 
 hipError_t gmm_launch_init(float4* state, int Kc, int Kd, int npix, const GmmConsts& c,
@@ -146,11 +149,12 @@ struct PbasStepArgs {
 
 hipError_t pbas_launch_init_state(const PbasPlanes& m, int npix, const PbasConsts& c,
                                   hipStream_t s);
+template <int NB>
 struct PbasBatch {
     int32_t n;
-    int32_t first[kBatchMax + 1];
-    int32_t tiles_x[kBatchMax];
-    PbasStepArgs a[kBatchMax];
+    int32_t first[NB + 1];
+    int32_t tiles_x[NB];
+    PbasStepArgs a[NB];
 };
 
 hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s);

@@ -32,12 +32,12 @@ constexpr int kBlock = 256;
 // from the constants (any other choice).  CV = 3: per-channel colour variances.
 // One launch steps b.n models (one for a single push): workgroup w takes pixels
 // 256 (w - first[i]) .. +255 of model i, first[i] <= w < first[i + 1].
-template <int KC, int KD, bool NT, bool GEN, int CV>
-__global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmBatch b) {
+template <int NB, int KC, int KD, bool NT, bool GEN, int CV>
+__global__ __launch_bounds__(kBlock) void gmm_step_kernel(GmmBatch<NB> b) {
     const int w = (int)blockIdx.x;
     int i = 0;
 #pragma unroll
-    for (int j = 1; j < kBatchMax; ++j) i += (j < b.n && w >= b.first[j]) ? 1 : 0;
+    for (int j = 1; j < NB; ++j) i += (j < b.n && w >= b.first[j]) ? 1 : 0;
     const GmmStepArgs& a = b.a[i];
     const int p = (w - b.first[i]) * kBlock + (int)threadIdx.x;
     if (p < a.npix) gmm_pixel<KC, KD, NT, GEN ? 2 : 0, GEN ? 2 : 0, CV>(a, p);
@@ -130,26 +130,53 @@ __global__ void gmm_import_kernel(float4* state, const float* in, int Kc, int Kd
     }
 }
 
-template <int KC, int KD, bool GEN, int CV>
-void launch_step_g(const GmmBatch& b, unsigned grid, hipStream_t s) {
+template <int NB, int KC, int KD, bool GEN, int CV>
+void launch_step_g(const GmmBatch<NB>& b, unsigned grid, hipStream_t s) {
     if (b.a[0].streaming)
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, true, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL((gmm_step_kernel<NB, KC, KD, true, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, b);
     else
-        hipLaunchKernelGGL((gmm_step_kernel<KC, KD, false, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, b);
+        hipLaunchKernelGGL((gmm_step_kernel<NB, KC, KD, false, GEN, CV>), dim3(grid), dim3(kBlock), 0, s, b);
 }
 
 // Kernel variant of a model's constants: 2 per-channel variances, 1 rate or decision
 // variant, 0 the defaults compiled in.
 int variant(const GmmConsts& c) { return c.var_mode ? 2 : ((c.rho_mode || c.decision) ? 1 : 0); }
 
-template <int KC, int KD>
-hipError_t launch_step_t(const GmmBatch& b, unsigned grid, hipStream_t s) {
+template <int NB, int KC, int KD>
+hipError_t launch_step_t(const GmmBatch<NB>& b, unsigned grid, hipStream_t s) {
     switch (variant(b.a[0].c)) {
-        case 2: launch_step_g<KC, KD, true, 3>(b, grid, s); break;
-        case 1: launch_step_g<KC, KD, true, 1>(b, grid, s); break;
-        default: launch_step_g<KC, KD, false, 1>(b, grid, s); break;
+        case 2: launch_step_g<NB, KC, KD, true, 3>(b, grid, s); break;
+        case 1: launch_step_g<NB, KC, KD, true, 1>(b, grid, s); break;
+        default: launch_step_g<NB, KC, KD, false, 1>(b, grid, s); break;
     }
     return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_batch(const GmmStepArgs* a, int n, int Kc, int Kd, hipStream_t s) {
+    GmmBatch<NB> b;
+    std::memset(&b, 0, sizeof b);
+    b.n = n;
+    int64_t grid = 0;
+    for (int i = 0; i < n; ++i) {
+        b.a[i] = a[i];
+        b.first[i] = (int32_t)grid;
+        grid += (a[i].npix + kBlock - 1) / kBlock;
+    }
+    for (int i = n; i <= NB; ++i) b.first[i] = (int32_t)grid;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    const unsigned g = (unsigned)grid;
+    switch (Kc * 8 + Kd) {
+        case 1 * 8 + 1: return launch_step_t<NB, 1, 1>(b, g, s);
+        case 2 * 8 + 2: return launch_step_t<NB, 2, 2>(b, g, s);
+        case 3 * 8 + 3: return launch_step_t<NB, 3, 3>(b, g, s);
+        case 4 * 8 + 4: return launch_step_t<NB, 4, 4>(b, g, s);
+        case 5 * 8 + 5: return launch_step_t<NB, 5, 5>(b, g, s);
+        case 6 * 8 + 6: return launch_step_t<NB, 6, 6>(b, g, s);
+        case 7 * 8 + 7: return launch_step_t<NB, 7, 7>(b, g, s);
+        case 7 * 8 + 3: return launch_step_t<NB, 7, 3>(b, g, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -165,30 +192,9 @@ int gmm_batch_key(const GmmStepArgs& a, int Kc, int Kd) {
 
 hipError_t gmm_launch_step_batch(const GmmStepArgs* a, int n, int Kc, int Kd, hipStream_t s) {
     if (n < 1 || n > kBatchMax) return hipErrorInvalidValue;
-    GmmBatch b;
-    std::memset(&b, 0, sizeof b);
-    b.n = n;
-    int64_t grid = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 1; i < n; ++i)
         if (gmm_batch_key(a[i], Kc, Kd) != gmm_batch_key(a[0], Kc, Kd)) return hipErrorInvalidValue;
-        b.a[i] = a[i];
-        b.first[i] = (int32_t)grid;
-        grid += (a[i].npix + kBlock - 1) / kBlock;
-    }
-    for (int i = n; i <= kBatchMax; ++i) b.first[i] = (int32_t)grid;
-    if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    const unsigned g = (unsigned)grid;
-    switch (Kc * 8 + Kd) {
-        case 1 * 8 + 1: return launch_step_t<1, 1>(b, g, s);
-        case 2 * 8 + 2: return launch_step_t<2, 2>(b, g, s);
-        case 3 * 8 + 3: return launch_step_t<3, 3>(b, g, s);
-        case 4 * 8 + 4: return launch_step_t<4, 4>(b, g, s);
-        case 5 * 8 + 5: return launch_step_t<5, 5>(b, g, s);
-        case 6 * 8 + 6: return launch_step_t<6, 6>(b, g, s);
-        case 7 * 8 + 7: return launch_step_t<7, 7>(b, g, s);
-        case 7 * 8 + 3: return launch_step_t<7, 3>(b, g, s);
-        default: return hipErrorInvalidValue;
-    }
+    return n == 1 ? launch_batch<1>(a, n, Kc, Kd, s) : launch_batch<kBatchMax>(a, n, Kc, Kd, s);
 }
 
 hipError_t gmm_launch_step(const GmmStepArgs& a, int Kc, int Kd, hipStream_t s) {

@@ -27,13 +27,13 @@ constexpr int class_min(int nmax) { return nmax <= 8 ? 2 : (nmax <= 40 ? nmax - 
 // model): the grid's y extent is too small for the tile rows of a tall image.  One
 // launch steps b.n models (one for a single push): workgroup w takes tile
 // w - first[i] of model i, first[i] <= w < first[i + 1].
-template <int NMAX, bool NT>
-__global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasBatch b) {
+template <int NB, int NMAX, bool NT>
+__global__ __launch_bounds__(kBlock) void pbas_step_kernel(PbasBatch<NB> b) {
     __shared__ PbasLds<NMAX> sh;
     const int w = (int)blockIdx.x;
     int i = 0;
 #pragma unroll
-    for (int j = 1; j < kBatchMax; ++j) i += (j < b.n && w >= b.first[j]) ? 1 : 0;
+    for (int j = 1; j < NB; ++j) i += (j < b.n && w >= b.first[j]) ? 1 : 0;
     const int local = w - b.first[i], tiles_x = b.tiles_x[i];
     pbas_tile<NMAX, class_min(NMAX), NT>(b.a[i], local % tiles_x, local / tiles_x, sh);
 }
@@ -128,10 +128,10 @@ __global__ void pbas_import_samples_kernel(uint4* quads, const uint32_t* in, int
 
 inline unsigned blocks1d(int n) { return (unsigned)((n + 255) / 256); }
 
-template <int NMAX>
-void launch_step_nt(const PbasBatch& b, dim3 grid, hipStream_t s) {
-    if (b.a[0].streaming) hipLaunchKernelGGL((pbas_step_kernel<NMAX, true>), grid, dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((pbas_step_kernel<NMAX, false>), grid, dim3(kBlock), 0, s, b);
+template <int NB, int NMAX>
+void launch_step_nt(const PbasBatch<NB>& b, dim3 grid, hipStream_t s) {
+    if (b.a[0].streaming) hipLaunchKernelGGL((pbas_step_kernel<NB, NMAX, true>), grid, dim3(kBlock), 0, s, b);
+    else hipLaunchKernelGGL((pbas_step_kernel<NB, NMAX, false>), grid, dim3(kBlock), 0, s, b);
 }
 
 // Register capacity for the N sample words: the smallest instantiated NMAX >= N
@@ -145,21 +145,42 @@ int nmax_class(int N) {
     }
 }
 
-void launch_step_n(const PbasBatch& b, dim3 grid, hipStream_t s) {
+template <int NB>
+void launch_step_n(const PbasBatch<NB>& b, dim3 grid, hipStream_t s) {
     switch (nmax_class(b.a[0].c.N)) {
-        case 8: launch_step_nt<8>(b, grid, s); break;
-        case 12: launch_step_nt<12>(b, grid, s); break;
-        case 16: launch_step_nt<16>(b, grid, s); break;
-        case 20: launch_step_nt<20>(b, grid, s); break;
-        case 24: launch_step_nt<24>(b, grid, s); break;
-        case 28: launch_step_nt<28>(b, grid, s); break;
-        case 32: launch_step_nt<32>(b, grid, s); break;
-        case 36: launch_step_nt<36>(b, grid, s); break;
-        case 40: launch_step_nt<40>(b, grid, s); break;
-        case 48: launch_step_nt<48>(b, grid, s); break;
-        case 56: launch_step_nt<56>(b, grid, s); break;
-        default: launch_step_nt<64>(b, grid, s); break;
+        case 8: launch_step_nt<NB, 8>(b, grid, s); break;
+        case 12: launch_step_nt<NB, 12>(b, grid, s); break;
+        case 16: launch_step_nt<NB, 16>(b, grid, s); break;
+        case 20: launch_step_nt<NB, 20>(b, grid, s); break;
+        case 24: launch_step_nt<NB, 24>(b, grid, s); break;
+        case 28: launch_step_nt<NB, 28>(b, grid, s); break;
+        case 32: launch_step_nt<NB, 32>(b, grid, s); break;
+        case 36: launch_step_nt<NB, 36>(b, grid, s); break;
+        case 40: launch_step_nt<NB, 40>(b, grid, s); break;
+        case 48: launch_step_nt<NB, 48>(b, grid, s); break;
+        case 56: launch_step_nt<NB, 56>(b, grid, s); break;
+        default: launch_step_nt<NB, 64>(b, grid, s); break;
     }
+}
+
+template <int NB>
+hipError_t launch_batch(const PbasStepArgs* a, int n, hipStream_t s) {
+    PbasBatch<NB> b;
+    std::memset(&b, 0, sizeof b);
+    b.n = n;
+    int64_t grid = 0;
+    for (int i = 0; i < n; ++i) {
+        b.a[i] = a[i];
+        b.tiles_x[i] = (a[i].W + kTileW - 1) / kTileW;
+        b.first[i] = (int32_t)grid;
+        // ceil(W/64) * ceil(H/4) <= H*W/256 + W/64 + H/4 + 1 < 2^27 tiles for H*W <= 2^28
+        grid += (int64_t)b.tiles_x[i] * ((a[i].H + kTileH - 1) / kTileH);
+    }
+    for (int i = n; i <= NB; ++i) b.first[i] = (int32_t)grid;
+    for (int i = n; i < NB; ++i) b.tiles_x[i] = 1;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    launch_step_n(b, dim3((unsigned)grid), s);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -179,24 +200,11 @@ int pbas_batch_key(const PbasStepArgs& a) {
 
 hipError_t pbas_launch_step_batch(const PbasStepArgs* a, int n, hipStream_t s) {
     if (n < 1 || n > kBatchMax) return hipErrorInvalidValue;
-    PbasBatch b;
-    std::memset(&b, 0, sizeof b);
-    b.n = n;
-    int64_t grid = 0;
     for (int i = 0; i < n; ++i) {
         const int key = pbas_batch_key(a[i]);
         if (key < 0 || key != pbas_batch_key(a[0])) return hipErrorInvalidValue;
-        b.a[i] = a[i];
-        b.tiles_x[i] = (a[i].W + kTileW - 1) / kTileW;
-        b.first[i] = (int32_t)grid;
-        // ceil(W/64) * ceil(H/4) <= H*W/256 + W/64 + H/4 + 1 < 2^27 tiles for H*W <= 2^28
-        grid += (int64_t)b.tiles_x[i] * ((a[i].H + kTileH - 1) / kTileH);
     }
-    for (int i = n; i <= kBatchMax; ++i) b.first[i] = (int32_t)grid;
-    for (int i = n; i < kBatchMax; ++i) b.tiles_x[i] = 1;
-    if (grid > 0x7fffffff) return hipErrorInvalidValue;
-    launch_step_n(b, dim3((unsigned)grid), s);
-    return hipGetLastError();
+    return n == 1 ? launch_batch<1>(a, n, s) : launch_batch<kBatchMax>(a, n, s);
 }
 
 hipError_t pbas_launch_step(const PbasStepArgs& a, hipStream_t s) {
