@@ -308,11 +308,11 @@ __device__ __forceinline__ float density_factor(float delta, float v, float s) {
 // A plane is stored only where one of the 4 pixels sharing the lane's 64-byte
 // sector of it (lanes 4i..4i+3: 16 bytes per pixel) may have changed it, so every
 // store still covers whole sectors.
-__device__ __forceinline__ bool sector_any(bool b) {
-    uint32_t v = b ? 1u : 0u;
-    v |= __shfl_xor(v, 1, 64);
-    v |= __shfl_xor(v, 2, 64);
-    return v != 0u;
+// Bit i of the result: bit i of `bits` set in any of lanes 4i..4i+3 (one plane per bit).
+__device__ __forceinline__ uint32_t sector_or(uint32_t bits) {
+    bits |= __shfl_xor(bits, 1, 64);
+    bits |= __shfl_xor(bits, 2, 64);
+    return bits;
 }
 
 template <int KC, int KD, bool NT, int RW = 2, int DEC = 2, int CV = 1>
@@ -380,9 +380,10 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
     mixture_step<KC, 3, false, CV>(mc, Xc, true, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_c,
                                a.c.v_min_c, used_c, dc, nullptr, rw, &chg_c, DEC ? &vsel_c : nullptr);
     // the colour means and variances are final: store them before the depth step
+    const uint32_t wc = sector_or(chg_c);
 #pragma unroll
     for (int k = 0; k < KC; ++k)
-        if (sector_any((chg_c >> k) & 1u))
+        if ((wc >> k) & 1u)
             st_state<NT>(so + (int64_t)k * a.npix + p, make_float4(mc.mu[k][0], mc.mu[k][1], mc.mu[k][2], mc.v[k]));
     mixture_step<KD, 1, false>(md, Xd, valid, a.c.alpha, lam2, a.c.T_bg, a.c.w_init, a.c.v_init_d,
                                a.c.v_min_d, used_d, dd, nullptr, rw, &chg_d, DEC ? &vsel_d : nullptr);
@@ -420,6 +421,7 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
         ex[L::mu_d(k)] = md.mu[k][0];
         ex[L::v_d(k)] = md.v[k];
     }
+    uint32_t che = 0u;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         bool ch = false;
@@ -430,10 +432,14 @@ __device__ __forceinline__ void gmm_pixel(const GmmStepArgs& a, int p) {
             else if (i < KC + 3 * KD) ch = ch || ((chg_d >> ((i - KC - KD) >> 1)) & 1u);
             else if (i < L::NX) ch = ch || ((chg_c >> ((i - KC - 3 * KD) >> 1)) & 1u);
         }
-        if (sector_any(ch))
+        che |= (ch ? 1u : 0u) << e;
+    }
+    const uint32_t we = sector_or(che);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if ((we >> e) & 1u)
             st_state<NT>(so + (int64_t)(KC + e) * a.npix + p,
                          make_float4(ex[4 * e + 0], ex[4 * e + 1], ex[4 * e + 2], ex[4 * e + 3]));
-    }
 }
 
 }  // namespace fgs
