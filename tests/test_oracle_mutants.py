@@ -133,6 +133,15 @@ PBAS_MUTANTS = [
      "ny, nx = ys + NB_DY[d], xs + NB_DX[d]", "ny, nx = ys + NB_DX[d], xs + NB_DY[d]"),
     ("no R floor", oracle.pbas.PbasRef, "step",
      "R_new = np.maximum(R_new, np.array(p.R_lower, f))", "R_new = R_new"),
+    ("draws: frame and block swapped in the counter", oracle.pbas, "pbas_draws",
+     "philox4x32_10(pix, np.uint64(t), np.uint64(c), np.uint64(0), k0, k1)",
+     "philox4x32_10(pix, np.uint64(c), np.uint64(t), np.uint64(0), k0, k1)"),
+    ("draws: self and neighbour blocks exchanged", oracle.pbas, "pbas_draws",
+     "return out[0], out[1]", "return out[1], out[0]"),
+    ("draws: key words exchanged", oracle.pbas, "pbas_draws",
+     "k0, k1 = seed_key(seed)", "k1, k0 = seed_key(seed)"),
+    ("draws: window keyed by its own width", oracle.pbas, "pbas_draws",
+     "pix = ys * np.uint64(W_img) + xs", "pix = ys * np.uint64(W) + xs"),
 ]
 
 OTHER_MUTANTS = [

@@ -178,6 +178,37 @@ def test_neighbour_writes_gathered_independently():
         np.testing.assert_array_equal(ref.samples, expect, err_msg=f"frame {t}")
 
 
+def test_draws_follow_the_counter_definition():
+    # R-17 written out for single pixels: block c of pixel (y, x) at frame t is
+    # Philox4x32-10 of the counter (y * W_img + x, t, c, 0) under the key (low 32 bits of
+    # the seed, high 32 bits), computed by the one-counter integer implementation with
+    # the key split by hand; block 0 serves the self-update, block 1 the neighbour
+    # update, word j channel j.  A seed whose halves differ, frames that differ from the
+    # block index, and windows placed in a wider image.
+    from oracle.philox import philox4x32_10_int
+    seed = 0x0123456789ABCDEF
+    key = (0x89ABCDEF, 0x01234567)
+    cases = [  # (H, W, t, origin or None, pixels (y, x) of the array)
+        (5, 7, 3, None, [(0, 0), (0, 6), (4, 0), (2, 3), (4, 6)]),
+        (3, 4, 12345, None, [(0, 1), (2, 3)]),
+        (4, 5, 2, (10, 20, 640), [(0, 0), (3, 4), (1, 2)]),
+        (2, 3, 0xFFFFFFF0, (479, 637, 640), [(0, 0), (1, 2)]),
+    ]
+    for H, W, t, origin, pts in cases:
+        w0, w1 = pbas_draws(H, W, t, seed, origin)
+        assert w0.shape == w1.shape == (H, W, 4) and w0.dtype == w1.dtype == np.uint32
+        y0, x0, W_img = origin if origin is not None else (0, 0, W)
+        for y, x in pts:
+            pix = (y0 + y) * W_img + (x0 + x)
+            for c, blk in ((0, w0), (1, w1)):
+                want = philox4x32_10_int((pix, t, c, 0), key)
+                assert tuple(int(v) for v in blk[y, x]) == want, (H, W, t, origin, y, x, c)
+    # the two blocks of a pixel-frame are different words (a self-update and a neighbour
+    # update drawn from one block would make this fail only by chance)
+    w0, w1 = pbas_draws(4, 4, 7, seed)
+    assert not np.array_equal(w0, w1)
+
+
 def test_window_model_matches_whole_image_except_ring_samples():
     # A window of a larger image drawn with the image's pixel indices: from the same state,
     # one frame gives the whole image's mask, R, T, S and D on the window, and its samples
