@@ -25,14 +25,17 @@ def _gpu():
     yield
 
 
-def _run_batched(specs, frames, seed):
-    """specs: [(algo, H, W, oracle params)]; all models on one stream, pushed together."""
+def _run_batched(specs, frames, seed, policy=None):
+    """specs: [(algo, H, W, oracle params)]; all models on one stream, pushed together;
+    `policy` an fgs_set_cache_policy value for every model (None: the automatic one)."""
     from paper_2002_00250_amd import fgs
     stream = torch.cuda.Stream()
     models, refs, scenes = [], [], []
     for k, (algo, H, W, p) in enumerate(specs):
         cp = _gmm_params_c(p) if algo == fgs.FGS_GMM else _pbas_params_c(p)
         models.append(fgs.Model(algo, H, W, cp, stream=stream))
+        if policy is not None:
+            fgs.fgs_set_cache_policy(models[-1].handle, policy)
         refs.append(GmmRef(H, W, p) if algo == fgs.FGS_GMM else PbasRef(H, W, p))
         scenes.append(Scene(preset("pbas_640x480", H=H, W=W, seed=seed + k)))
     diff = [0] * len(specs)
@@ -98,6 +101,20 @@ def test_gmm_and_pbas_in_one_call():
     specs = [(fgs.FGS_PBAS, 20, 70, PbasParams(N=6, seed=9)), (fgs.FGS_GMM, 20, 70, GmmParams(Kc=5, Kd=5)),
              (fgs.FGS_PBAS, 17, 90, PbasParams(N=6, seed=10)), (fgs.FGS_GMM, 31, 33, GmmParams(Kc=5, Kd=5))]
     _all_equal(_run_batched(specs, 12, seed=80))
+
+
+def test_benchmark_kernel_instances_on_distinct_models():
+    # The instances the benchmark times: 8 GMM Kc = Kd = 5 models (default rate and
+    # decision) in one launch and 4 PBAS N = 35 models in one launch, state streamed with
+    # non-temporal accesses.  Small ragged frames, every model its own scene and seed, so a
+    # workgroup that took another model's arguments would show.
+    from paper_2002_00250_amd import fgs
+    G, P = fgs.FGS_GMM, fgs.FGS_PBAS
+    sizes = [(37, 129), (48, 80), (1, 257), (64, 64), (33, 70), (20, 300), (45, 131), (17, 95)]
+    specs = [(G, H, W, GmmParams(Kc=5, Kd=5)) for H, W in sizes]
+    specs += [(P, H, W, PbasParams(N=35, seed=100 + k))
+              for k, (H, W) in enumerate([(21, 70), (45, 131), (9, 130), (64, 66)])]
+    _all_equal(_run_batched(specs, 50, seed=120, policy=fgs.FGS_CACHE_STREAM))
 
 
 def test_argument_checks_leave_models_untouched():

@@ -1,7 +1,8 @@
-"""Multi-stream server: every stream's masks in the batched mix are identical to the same
-stream driven alone through fgs_push_frame; admission by HBM budget; back-pressure; close
-with frames queued; the 32-stream, 30 fps mixed-resolution workload within one frame
-period at p99."""
+"""Multi-stream server: every stream's masks in the batched mix are identical to the
+oracle's run of that stream and to the same stream driven alone through fgs_push_frame;
+admission by HBM budget; back-pressure; close with frames queued; the 32-stream, 30 fps
+mixed-resolution workload within one frame period at p99, three of its streams compared
+with the oracle over every served frame."""
 import numpy as np
 import pytest
 
@@ -9,6 +10,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from gpu_util import log  # noqa: E402
+from oracle.gmm import GmmParams, GmmRef  # noqa: E402
+from oracle.pbas import PbasParams, PbasRef  # noqa: E402
+from oracle_runs import OracleRuns, make_job, windows  # noqa: E402
 from synth import Scene, preset  # noqa: E402
 
 
@@ -39,6 +43,23 @@ def _params(algo, K=5, N=20, seed=None, gmm_variant=False):
 def _frames(H, W, n, seed):
     sc = Scene(preset("pbas_640x480", H=H, W=W, seed=seed))
     return [sc.frame(t)[:2] for t in range(n)]
+
+
+def _oracle_params(algo, p):
+    """The oracle's constants for a stream opened with the library's params `p` (the
+    library's defaults are the oracle's; only the fields these tests change are copied)."""
+    from paper_2002_00250_amd import fgs
+    if algo == fgs.FGS_GMM:
+        return GmmParams(Kc=p.Kc, Kd=p.Kd, rho_mode=p.rho_mode, decision=p.decision)
+    return PbasParams(N=p.N, seed=p.seed)
+
+
+def _oracle(algo, H, W, params, frames):
+    """The oracle's masks for a stream's frames, from frame 0."""
+    from paper_2002_00250_amd import fgs
+    op = _oracle_params(algo, params)
+    ref = GmmRef(H, W, op) if algo == fgs.FGS_GMM else PbasRef(H, W, op)
+    return [ref.step(rgb, dep) for rgb, dep in frames]
 
 
 def _alone(algo, H, W, params, frames):
@@ -86,9 +107,12 @@ def test_mix_equals_alone(gmm_variant):
         f"({st['mean_batch_frames']:.2f} per batch)")
     for sid, algo, H, W, p, fr in streams:
         ref = _alone(algo, H, W, p, fr)
+        orc = _oracle(algo, H, W, p, fr)
         diff = sum(int((a != b).sum()) for a, b in zip(got[sid], ref))
-        log(f"stream {sid} ({'GMM' if algo == fgs.FGS_GMM else 'PBAS'} {H}x{W}): {diff} mask pixels differ from alone")
-        assert diff == 0
+        odiff = sum(int((a != b).sum()) for a, b in zip(got[sid], orc))
+        log(f"stream {sid} ({'GMM' if algo == fgs.FGS_GMM else 'PBAS'} {H}x{W}): {odiff} mask pixels "
+            f"differ from the oracle, {diff} from the stream alone")
+        assert len(got[sid]) == T and odiff == 0 and diff == 0
     srv.destroy()
 
 
@@ -113,10 +137,12 @@ def test_pbas_n_up_to_40_in_the_mix_equals_alone():
             got[sid].append(m)
     for sid, algo, H, W, p, fr in streams:
         ref = _alone(algo, H, W, p, fr)
+        orc = _oracle(algo, H, W, p, fr)
         diff = sum(int((a != b).sum()) for a, b in zip(got[sid], ref))
+        odiff = sum(int((a != b).sum()) for a, b in zip(got[sid], orc))
         log(f"server N<=40 mix: stream {sid} ({'GMM' if algo == fgs.FGS_GMM else 'PBAS N=%d' % p.N} {H}x{W}): "
-            f"{diff} mask pixels differ from alone")
-        assert diff == 0
+            f"{odiff} mask pixels differ from the oracle, {diff} from alone")
+        assert odiff == 0 and diff == 0
     srv.destroy()
 
 
@@ -336,14 +362,49 @@ def test_32_streams_30fps_mixed_resolution():
         f"max {lat.max() * 1e3:.2f} ms; {st['mean_batch_frames']:.2f} frames/batch; "
         f"{st['mpix_frames_per_s']:.1f} Mpx-f/s served (offered {offered:.1f})")
     assert p99 < 1.0 / 30
-    # masks of three streams equal the same frames pushed alone (warm-up frames first)
-    for i in (0, 13, 31):
+    # masks of three streams equal the oracle's run and the same frames pushed alone
+    # (warm-up frames first); the served frames cycle through 4 scene frames, counted from
+    # 0 again in the measured run.  The oracle follows the two PBAS streams in windows
+    # with the neighbour updates' propagation margin, in child processes.
+    kept = (0, 13, 31)
+    jobs, owner = [], {}
+    for i in kept:
         algo, H, W, p = meta[i]
-        seq = [loads[i].frames[k % 4] for k in range(len(warm[i].latencies))] + \
-              [loads[i].frames[k % 4] for k in range(len(loads[i].latencies))]
-        ref = _alone(algo, H, W, p, seq)[len(warm[i].latencies):]
-        got = [m for _, m in sorted(loads[i].masks, key=lambda x: x[0])]
-        diff = sum(int((a != b).sum()) for a, b in zip(got, ref))
-        log(f"stream {i}: {diff} mask pixels differ from alone over {len(got)} frames")
-        assert len(got) == len(ref) and diff == 0
+        nw, nl = len(warm[i].latencies), len(loads[i].latencies)
+        ids = [k % 4 for k in range(nw)] + [k % 4 for k in range(nl)]
+        kind = "gmm" if algo == fgs.FGS_GMM else "pbas"
+        op = _oracle_params(algo, p)
+        prm = dict(Kc=op.Kc, Kd=op.Kd) if kind == "gmm" else dict(N=op.N, seed=op.seed)
+        grid = (1, 1) if kind == "gmm" else ((2, 4) if H >= 720 else (1, 2))
+        margin = 0 if kind == "gmm" else max(0, len(ids) - op.N)
+        owner[i] = []
+        for win, own in windows(H, W, *grid, margin):
+            owner[i].append(len(jobs))
+            jobs.append(make_job(kind, "pbas_640x480", dict(H=H, W=W, seed=300 + i), prm, len(ids), H, W,
+                                 win, own, frame_ids=ids))
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        runs = OracleRuns(jobs, td)
+        try:
+            for i in kept:
+                algo, H, W, p = meta[i]
+                seq = [loads[i].frames[k % 4] for k in range(len(warm[i].latencies))] + \
+                      [loads[i].frames[k % 4] for k in range(len(loads[i].latencies))]
+                nw = len(warm[i].latencies)
+                ref = _alone(algo, H, W, p, seq)[nw:]
+                got = [m for _, m in sorted(loads[i].masks, key=lambda x: x[0])]
+                diff = sum(int((a != b).sum()) for a, b in zip(got, ref))
+                exp = np.zeros((len(seq), H, W), bool)
+                for j in owner[i]:
+                    oy, ox, oh, ow = jobs[j]["own"]
+                    mk = runs.result(j)["masks"]
+                    exp[:, oy:oy + oh, ox:ox + ow] = np.unpackbits(mk, axis=1)[:, :oh * ow].reshape(
+                        len(seq), oh, ow).astype(bool)
+                odiff = sum(int(((a != 0) != b).sum()) for a, b in zip(got, exp[nw:]))
+                log(f"stream {i} ({'GMM' if algo == fgs.FGS_GMM else 'PBAS'} {H}x{W}): over {len(got)} served "
+                    f"frames (after {nw} warm-up frames) {odiff} mask pixels differ from the oracle, "
+                    f"{diff} from alone")
+                assert len(got) == len(ref) and odiff == 0 and diff == 0
+        finally:
+            runs.close()
     srv.destroy()
