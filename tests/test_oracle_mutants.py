@@ -20,6 +20,7 @@ import test_oracle_depth
 import test_oracle_gmm
 import test_oracle_metrics
 import test_oracle_pbas
+import test_oracle_pbas_gradient
 import test_oracle_philox
 import test_oracle_postfilter
 
@@ -144,6 +145,25 @@ PBAS_MUTANTS = [
      "pix = ys * np.uint64(W_img) + xs", "pix = ys * np.uint64(W) + xs"),
 ]
 
+GRADIENT_MUTANTS = [
+    ("gradient weight from this frame's mean", oracle.pbas.PbasRef, "_step_gradient",
+     "gradient_mean(self.gsum_prev, H * W)", "gradient_mean(gsum, H * W)"),
+    ("no floor under the gradient mean", oracle.pbas.PbasRef, "_step_gradient",
+     "np.maximum(gradient_mean(self.gsum_prev, H * W), f(1.0))", "gradient_mean(self.gsum_prev, H * W)"),
+    ("neighbour keeps its old magnitude", oracle.pbas.PbasRef, "_step_gradient",
+     "self.gsamples[kk[c], ny[c], nx[c], js[c]] = M[ny[c], nx[c], js[c]]", "pass"),
+    ("self-update keeps the old magnitude", oracle.pbas.PbasRef, "_step_gradient",
+     "self.gsamples[ks[c], ys[c], xs[c], js[c]] = M[ys[c], xs[c], js[c]]", "pass"),
+    ("Sobel border padded with zeros", oracle.pbas, "sobel_l1_magnitude",
+     'np.pad(np.asarray(plane, np.int32), 1, mode="edge")', 'np.pad(np.asarray(plane, np.int32), 1, mode="constant")'),
+    ("Sobel y response taken along x", oracle.pbas, "sobel_l1_magnitude",
+     "gy = (at(1, -1) + 2 * at(1, 0) + at(1, 1)) - (at(-1, -1) + 2 * at(-1, 0) + at(-1, 1))", "gy = gx"),
+    ("gradient S misses the replaced D", oracle.pbas.PbasRef, "_step_gradient",
+     "self.S[ys, xs, js] = (self.S[ys, xs, js] - old) + dm", "self.S[ys, xs, js] = self.S[ys, xs, js] + dm"),
+    ("gradient term unweighted", oracle.pbas.PbasRef, "_step_gradient",
+     "dist[..., :3] = wgt * dm + dv[..., :3]", "dist[..., :3] = dm + dv[..., :3]"),
+]
+
 OTHER_MUTANTS = [
     ("depth code rounds down", oracle.depth, "depth_q8", "q = (255 * d + m // 2) // m", "q = (255 * d) // m",
      test_oracle_depth),
@@ -191,6 +211,12 @@ def test_pbas_pins_catch(monkeypatch, what, owner, name, old, new):
     assert _caught(test_oracle_pbas) is not None, what
 
 
+@pytest.mark.parametrize("what,owner,name,old,new", GRADIENT_MUTANTS, ids=[m[0] for m in GRADIENT_MUTANTS])
+def test_gradient_pins_catch(monkeypatch, what, owner, name, old, new):
+    _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [test_oracle_pbas_gradient])
+    assert _caught(test_oracle_pbas_gradient) is not None, what
+
+
 @pytest.mark.parametrize("what,owner,name,old,new,pins", OTHER_MUTANTS, ids=[m[0] for m in OTHER_MUTANTS])
 def test_other_pins_catch(monkeypatch, what, owner, name, old, new, pins):
     _patch(monkeypatch, owner, name, _mutant(getattr(owner, name), old, new), [pins])
@@ -216,5 +242,5 @@ def test_philox_pin_catches_swapped_key_words(monkeypatch, rocrand_probe):
 
 def test_unmutated_oracle_passes_its_pins():
     for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics, test_oracle_adjoint,
-                test_oracle_postfilter):
+                test_oracle_postfilter, test_oracle_pbas_gradient):
         assert _caught(mod) is None, mod.__name__
