@@ -17,6 +17,7 @@ Modules
 ``pbas``      RGB-D Pixel-Based Adaptive Segmenter step (Sec. 3.2)
 ``metrics``   PWC / FNR / FPR / Si quality indicators (Sec. 5)
 ``postfilter`` median post-filter of a binary mask (base PBAS method's smoothing)
+``static``    static-object detection on a mask sequence (reading of Sec. 6's future work)
 
 Floating point follows IEEE binary32 (or binary64 for the gradient reference)
 with every operation rounded separately, in the order written in each

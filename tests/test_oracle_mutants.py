@@ -15,6 +15,7 @@ import oracle.metrics
 import oracle.pbas
 import oracle.philox
 import oracle.postfilter
+import oracle.static
 import test_oracle_adjoint
 import test_oracle_depth
 import test_oracle_gmm
@@ -23,6 +24,7 @@ import test_oracle_pbas
 import test_oracle_pbas_gradient
 import test_oracle_philox
 import test_oracle_postfilter
+import test_oracle_static
 
 
 def _mutant(func, old, new):
@@ -165,6 +167,13 @@ GRADIENT_MUTANTS = [
 ]
 
 OTHER_MUTANTS = [
+    ("static: run must exceed M", oracle.static.StaticRef, "step",
+     "self.count >= self.M", "self.count > self.M", test_oracle_static),
+    ("static: run not reset by background", oracle.static.StaticRef, "step",
+     "np.minimum(self.count + 1, COUNTER_MAX), 0)", "np.minimum(self.count + 1, COUNTER_MAX), self.count)",
+     test_oracle_static),
+    ("static: counter not saturated", oracle.static.StaticRef, "step",
+     "np.minimum(self.count + 1, COUNTER_MAX)", "self.count + 1", test_oracle_static),
     ("depth code rounds down", oracle.depth, "depth_q8", "q = (255 * d + m // 2) // m", "q = (255 * d) // m",
      test_oracle_depth),
     ("upscale takes corners", oracle.depth, "upscale_nearest",
@@ -242,5 +251,5 @@ def test_philox_pin_catches_swapped_key_words(monkeypatch, rocrand_probe):
 
 def test_unmutated_oracle_passes_its_pins():
     for mod in (test_oracle_gmm, test_oracle_pbas, test_oracle_depth, test_oracle_metrics, test_oracle_adjoint,
-                test_oracle_postfilter, test_oracle_pbas_gradient):
+                test_oracle_postfilter, test_oracle_pbas_gradient, test_oracle_static):
         assert _caught(mod) is None, mod.__name__
