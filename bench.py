@@ -1,9 +1,12 @@
 """Throughput of the RGB-D GMM + PBAS classify-and-update step on one MI355X.
 
-A step pushes one 1280x720 RGB-D frame through a GMM model (Kc = Kd = 5) and through a
-PBAS model (N = 35): two kernel launches, state read and written once each, masks
-written.  Frames are synthetic (8 moving objects with shadows), generated before the
-timed region and resident in HBM.  Prints one JSON line.
+A step pushes one 1280x720 RGB-D frame through each of 8 GMM models (Kc = Kd = 5) and
+4 PBAS models (N = 35): one launch per kind, state read and written once each, masks
+written.  Frames are synthetic (8 moving objects with shadows), distinct, generated
+before the timed region and resident in HBM; every model first runs untimed through the
+sequence's first frames (default 100) so that the timed frames meet it in its steady
+state.  Then the 32-stream serving workload gives p50 / p99 frame latency, and the CPU
+oracle is timed on a bounded sample.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -42,12 +45,43 @@ def kernel_entry(avg_ms, bytes_per_px, gbs, profile, launches_per_step, models_p
     """Per-kernel figures of the default benchmark (None if the kernel did not run)."""
     if not launches_per_step:
         return None
-    return {"avg_ms": round(avg_ms, 5), "launches_per_step": launches_per_step,
-            "models_per_launch": models_per_launch, "bytes_per_px": bytes_per_px,
-            "GBs": round(gbs, 1), "traffic": measured_traffic(profile),
-            "Mpx_per_s": round(models_per_launch * H * W / (avg_ms * 1e-3) / 1e6, 1),
-            "frac": round(gbs / HBM_PEAK_GBS, 4),
-            "share_of_step": round(launches_per_step * avg_ms * 1e-3 / step_s, 4)}
+    traffic = measured_traffic(profile)
+    out = {"avg_ms": round(avg_ms, 5), "launches_per_step": launches_per_step,
+           "models_per_launch": models_per_launch, "bytes_per_px": bytes_per_px,
+           "GBs": round(gbs, 1), "traffic": traffic,
+           "Mpx_per_s": round(models_per_launch * H * W / (avg_ms * 1e-3) / 1e6, 1),
+           "frac": round(gbs / HBM_PEAK_GBS, 4),
+           "share_of_step": round(launches_per_step * avg_ms * 1e-3 / step_s, 4)}
+    if traffic is not None:
+        out["GBs_from_traffic"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+        out["traffic_bytes_per_px"] = round(traffic / (models_per_launch * H * W), 1)
+    return out
+
+
+PROFILE_FILES = {"gmm": "gmm_step_1280x720_k5.txt", "pbas": "pbas_step_1280x720_n35.txt"}
+
+
+def roofline_entry(kind, avg_ms, achieved_gbs, models_per_launch, bytes_per_px):
+    """The roofline object of the dominant kernel.  achieved / frac count algorithmic bytes
+    (the method's state read and written once, input and mask) per launch over the launch's
+    average duration; traffic is the HBM bytes per launch rocprofv3 measured (FETCH_SIZE +
+    WRITE_SIZE, each scaled by what it reads for a plain copy), and *_from_traffic put those
+    bytes over the same duration."""
+    npx = H * W
+    traffic = measured_traffic(PROFILE_FILES[kind])
+    out = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kind + "_step",
+           "algorithmic_bytes_per_launch": int(models_per_launch * bytes_per_px * npx),
+           "algorithmic_bytes_per_px": bytes_per_px}
+    if traffic is not None:
+        tg = traffic / (avg_ms * 1e-3) / 1e9
+        out.update(traffic_bytes_per_px=round(traffic / (models_per_launch * npx), 1),
+                   achieved_from_traffic=round(tg, 1), frac_from_traffic=round(tg / HBM_PEAK_GBS, 4))
+    out["note"] = ("achieved and frac: algorithmic bytes per launch / average launch time (HIP events on the "
+                   "launch stream); traffic: measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                   "profiles/" + PROFILE_FILES[kind] + "), achieved_from_traffic and frac_from_traffic: those "
+                   "bytes over the same time")
+    return out
 
 
 def _kv(path):
@@ -120,6 +154,37 @@ def _oracle_stream(rgb, depth, n_g, n_p, barrier=None):
     return tg / n_g, tp / n_p
 
 
+def _oracle_small_configs():
+    """The oracle on one thread at the two parity workloads: GMM Kc = Kd = 3 at 320x240 and
+    PBAS N = 20 at 640x480 (its 20 fill frames untimed)."""
+    from oracle.gmm import GmmParams, GmmRef
+    from oracle.pbas import PbasParams, PbasRef
+    from synth import Scene, preset
+    res = []
+    sc = Scene(preset("gmm_320x240"))
+    fr = [sc.frame(t)[:2] for t in range(21)]
+    g = GmmRef(240, 320, GmmParams(Kc=3, Kd=3))
+    g.step(*fr[0])
+    t0 = time.perf_counter()
+    for f in fr[1:]:
+        g.step(*f)
+    dt = (time.perf_counter() - t0) / 20
+    res.append({"workload": "GMM Kc=Kd=3, 320x240", "frames": 20, "value": round(240 * 320 / dt / 1e6, 4),
+                "unit": "Mpixel-frames/s", "cores": 1})
+    sc = Scene(preset("pbas_640x480"))
+    fr = [sc.frame(t)[:2] for t in range(28)]
+    p = PbasRef(480, 640, PbasParams(N=20))
+    for f in fr[:20]:
+        p.step(*f)
+    t0 = time.perf_counter()
+    for f in fr[20:]:
+        p.step(*f)
+    dt = (time.perf_counter() - t0) / 8
+    res.append({"workload": "PBAS N=20, 640x480", "frames": 8, "value": round(480 * 640 / dt / 1e6, 4),
+                "unit": "Mpixel-frames/s", "cores": 1})
+    return res
+
+
 _PAR = {}
 
 
@@ -149,6 +214,7 @@ def cpu_baseline(rgb, depth, procs: int):
                sample=f"numpy oracle, 1280x720: {n_g} GMM K=5 frames ({sg * n_g:.1f} s) + {n_p} PBAS "
                       f"N=35 updating frames ({sp * n_p:.1f} s), one host thread; step = one GMM + "
                       f"one PBAS frame; CPU: {cpu_model()}")
+    out["configs"] = _oracle_small_configs()
     if procs > 1:
         import multiprocessing as mp
         ctx = mp.get_context("fork")  # the workers only run numpy
@@ -167,18 +233,21 @@ def cpu_baseline(rgb, depth, procs: int):
     return out
 
 
-def serving_main(args):
+SERVE_SIZES = [(240, 424)] * 12 + [(480, 640)] * 12 + [(720, 1280)] * 8
+
+
+def serving_run(warm_s: float, seconds: float, saturate_s: float = 0.0) -> dict:
     """The 32-stream serving workload: 12x 424x240, 12x 640x480, 8x 1280x720, even streams
-    GMM K=5, odd PBAS N=20, frames at 30 fps (random phase, +-5 ms jitter); then the same
-    streams at saturation (every ring kept full) for the aggregate capacity."""
+    GMM K=5, odd PBAS N=20, frames at 30 fps (random phase, +-5 ms jitter), after `warm_s`
+    seconds of the same load untimed (PBAS fills its samples); with saturate_s > 0 the same
+    streams then run at saturation (every ring kept full) for the aggregate capacity."""
     import threading
     from paper_2002_00250_amd import fgs
     from paper_2002_00250_amd.serving import Server, StreamLoad, run_camera_load
     from synth import Scene, preset
-    sizes = [(240, 424)] * 12 + [(480, 640)] * 12 + [(720, 1280)] * 8
-    srv = Server(64 << 30, 32, gmm_K=5, pbas_N_max=24)
+    srv = Server(64 << 30, 32)
     loads = []
-    for i, (h, w) in enumerate(sizes):
+    for i, (h, w) in enumerate(SERVE_SIZES):
         if i % 2 == 0:
             p = fgs.fgs_gmm_params_default()
             p.Kc = p.Kd = 5
@@ -191,57 +260,73 @@ def serving_main(args):
         sid = srv.open(algo, h, w, p)
         sc = Scene(preset("hd_1280x720", H=h, W=w, seed=300 + i))
         loads.append(StreamLoad(sid, [sc.frame(t)[:2] for t in range(4)]))
-    run_camera_load(srv, [StreamLoad(l.sid, l.frames) for l in loads], duration_s=1.0, seed=1)
+    run_camera_load(srv, [StreamLoad(l.sid, l.frames) for l in loads], duration_s=warm_s, seed=1)
     srv.reset_stats()
-    lat, wall = run_camera_load(srv, loads, duration_s=args.serve_seconds, seed=2)
+    lat, wall = run_camera_load(srv, loads, duration_s=seconds, seed=2)
     st = srv.stats()
-    offered = sum(h * w for h, w in sizes) * 30 / 1e6
+    offered = sum(h * w for h, w in SERVE_SIZES) * 30 / 1e6
+    out = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+           "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+           "max_ms": round(float(lat.max()) * 1e3, 4),
+           "frames": int(lat.size), "frame_period_ms": round(1000 / 30, 3),
+           "served_Mpx_frames_per_s": round(st["mpix_frames_per_s"], 2),
+           "offered_Mpx_frames_per_s": round(offered, 2),
+           "frames_per_batch": round(st["mean_batch_frames"], 3),
+           "seconds": seconds, "warmup_seconds": warm_s,
+           "workload": "32 streams: 12x 424x240, 12x 640x480, 8x 1280x720; even GMM K=5, odd PBAS N=20; "
+                       "30 fps, +-5 ms jitter; latency = frame arrival to mask on the host"}
+    if saturate_s > 0:
+        # saturation: one thread per stream keeps its ring full for the same duration
+        srv.reset_stats()
+        stop = [False]
 
-    # saturation: one thread per stream keeps its ring full for the same duration
-    srv.reset_stats()
-    stop = [False]
-
-    def pump(ld):
-        tickets, k = [], 0
-        while not stop[0]:
-            rgb, dep = ld.frames[k % len(ld.frames)]
-            try:
-                tickets.append(srv.submit(ld.sid, rgb, dep))
-                k += 1
-            except fgs.FgsError:
-                srv.wait(tickets.pop(0))
-        for t in tickets:
-            srv.wait(t)
-    ths = [threading.Thread(target=pump, args=(ld,)) for ld in loads]
-    for t in ths:
-        t.start()
-    time.sleep(args.serve_seconds)
-    stop[0] = True
-    for t in ths:
-        t.join()
-    sat = srv.stats()
+        def pump(ld):
+            tickets, k = [], 0
+            while not stop[0]:
+                rgb, dep = ld.frames[k % len(ld.frames)]
+                try:
+                    tickets.append(srv.submit(ld.sid, rgb, dep))
+                    k += 1
+                except fgs.FgsError:
+                    srv.wait(tickets.pop(0))
+            for t in tickets:
+                srv.wait(t)
+        ths = [threading.Thread(target=pump, args=(ld,)) for ld in loads]
+        for t in ths:
+            t.start()
+        time.sleep(saturate_s)
+        stop[0] = True
+        for t in ths:
+            t.join()
+        sat = srv.stats()
+        out["saturated"] = {"Mpx_frames_per_s": round(sat["mpix_frames_per_s"], 1),
+                            "frames_per_batch": round(sat["mean_batch_frames"], 2),
+                            "p50_ms": round(sat["p50_latency_s"] * 1e3, 3),
+                            "p99_ms": round(sat["p99_latency_s"] * 1e3, 3)}
     srv.destroy()
+    return out
+
+
+def serving_main(args):
+    """--serving: the serving workload alone, p99 latency as the value."""
+    r = serving_run(1.0, args.serve_seconds, saturate_s=args.serve_seconds)
     out = {
         "metric": "p99 frame latency (32 mixed-resolution RGB-D streams at 30 fps)",
-        "value": round(float(np.percentile(lat, 99)) * 1e3, 4),
+        "value": r["p99_ms"],
         "unit": "ms",
         "n_gpus": 1,
         "higher_is_better": False,
-        "frames": int(lat.size),
-        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
-        "max_ms": round(float(lat.max()) * 1e3, 4),
-        "frame_period_ms": round(1000 / 30, 3),
-        "served_Mpx_frames_per_s": round(st["mpix_frames_per_s"], 2),
-        "offered_Mpx_frames_per_s": round(offered, 2),
-        "frames_per_batch": round(st["mean_batch_frames"], 3),
-        "saturated": {"Mpx_frames_per_s": round(sat["mpix_frames_per_s"], 1),
-                      "frames_per_batch": round(sat["mean_batch_frames"], 2),
-                      "p50_ms": round(sat["p50_latency_s"] * 1e3, 3),
-                      "p99_ms": round(sat["p99_latency_s"] * 1e3, 3)},
+        "frames": r["frames"],
+        "p50_ms": r["p50_ms"],
+        "max_ms": r["max_ms"],
+        "frame_period_ms": r["frame_period_ms"],
+        "served_Mpx_frames_per_s": r["served_Mpx_frames_per_s"],
+        "offered_Mpx_frames_per_s": r["offered_Mpx_frames_per_s"],
+        "frames_per_batch": r["frames_per_batch"],
+        "saturated": r["saturated"],
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "32 streams: 12x 424x240, 12x 640x480, 8x 1280x720; even GMM K=5, odd PBAS N=20; "
-                               "30 fps, +-5 ms jitter", "seconds": args.serve_seconds},
+        "config": {"workload": r["workload"], "seconds": args.serve_seconds},
     }
     print(json.dumps(out), flush=True)
 
@@ -442,7 +527,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--frames", type=int, default=64, help="distinct pre-staged frames (cycled)")
+    ap.add_argument("--start", type=int, default=100,
+                    help="frames every model runs through untimed before the warm-up (PBAS fill frames "
+                         "included), so that the timed frames come from a model in its steady state")
     ap.add_argument("--models", type=lambda v: tuple(int(x) for x in v.split(",")), default=(8, 4),
                     help="GMM,PBAS model counts stepped round-robin (default 8,4: 2.4 GB of live state)")
     ap.add_argument("--per-model", action="store_true",
@@ -456,6 +543,8 @@ def main():
                     help="processes for the aggregate oracle baseline (1: single thread only)")
     ap.add_argument("--serving", action="store_true", help="run the 32-stream serving workload instead")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave the serving workload (p50/p99 latency) out of the default line")
     ap.add_argument("--adjoint", action="store_true", help="time the GMM adjoint window step instead")
     ap.add_argument("--table1", action="store_true", help="time the paper's Table 1 resolutions instead")
     ap.add_argument("--eval", action="store_true", help="time the evaluation counters instead")
@@ -490,7 +579,12 @@ def main():
     # "create a private stream"); every launch and every timing event goes on it.
     stream = torch.cuda.Stream(dev)
     torch.cuda.set_stream(stream)
-    rgb_h, dep_h = make_frames(args.frames, args.workers)
+    n_g, n_p = args.models
+    L0 = n_g + n_p
+    # every frame pushed is a distinct frame of the sequence: model j takes frame t + j at
+    # step t, for t = 0 .. start + warmup + steps - 1
+    F = args.start + args.warmup + args.steps + max(0, L0 - 1)
+    rgb_h, dep_h = make_frames(F, args.workers)
     rgb = torch.from_numpy(rgb_h).to(dev)
     dep = torch.from_numpy(dep_h.view(np.int16)).to(dev)
 
@@ -500,25 +594,17 @@ def main():
     pp.N = N_PBAS
     # Independent camera models stepped round-robin, their live state far beyond the
     # 256 MB Infinity Cache, so every launch runs against HBM.
-    n_g, n_p = args.models
     S = max(1, args.streams)
     streams = [stream] + [torch.cuda.Stream(dev) for _ in range(S - 1)]
     models = [(fgs.Model(fgs.FGS_GMM, H, W, gp, stream=streams[j % S]), "gmm") for j in range(n_g)] + \
              [(fgs.Model(fgs.FGS_PBAS, H, W, pp, stream=streams[(n_g + j) % S]), "pbas") for j in range(n_p)]
     live = sum(fgs.fgs_device_bytes(m.handle) for m, _ in models)
-    F = args.frames
     rs, ds = 3 * W, 2 * W
 
-    def push(j, i):   # model j sees the frame sequence from its own offset
-        f = (i + 7 * j) % F
+    def push(j, i):   # model j sees the sequence from its own offset j
+        f = i + j
         fgs.fgs_push_frame(models[j][0].handle, rgb[f].data_ptr(), rs, dep[f].data_ptr(), ds,
                            fgs.FGS_MEM_DEVICE)
-
-    # PBAS models first fill their N samples from N frames (set-up, not a step).
-    for i in range(N_PBAS):
-        for j, (_, kind) in enumerate(models):
-            if kind == "pbas":
-                push(j, i)
 
     # A step pushes a frame to every GMM model, then to every PBAS model, on one stream:
     # by default one fgs_push_frames call per kind, i.e. one launch for up to 8 models
@@ -537,17 +623,19 @@ def main():
             for j in js:
                 push(j, i)
             return
-        fs = [(i + 7 * j) % F for j in js]
+        fs = [i + j for j in js]
         fgs.fgs_push_frames([models[j][0].handle for j in js], [rgb[f].data_ptr() for f in fs], [rs] * len(js),
                             [dep[f].data_ptr() for f in fs], [ds] * len(js))
     g_js, p_js = list(range(n_g)), list(range(n_g, L))
-    for i in range(args.warmup):
+    # untimed: frames 0 .. start - 1 (the PBAS models' N fill frames among them), then the
+    # warm-up steps
+    for i in range(args.start + args.warmup):
         for js in (g_js, p_js):
             if js:
-                push_kind(js, N_PBAS + i)
+                push_kind(js, i)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * K + 1)]
-    base = N_PBAS + args.warmup
+    base = args.start + args.warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(K):
@@ -585,6 +673,9 @@ def main():
 
     wall = t1 - t0
     npx = H * W
+    frames_cfg = {"timed_frames": [base, base + K - 1], "untimed_frames": base,
+                  "frame_sequence": "non-repeating frames of the 1280x720 sequence; at step t model j "
+                                    "takes frame t + j"}
     value = L * npx * K / wall / 1e6
     g_b, p_b = gmm_bytes_per_px(), pbas_bytes_per_px()
     g_gbs = g_per * g_b * npx / (gmm_ms * 1e-3) / 1e9 if n_g else 0.0
@@ -604,7 +695,7 @@ def main():
             "config": {"workload": f"RGB-D 1280x720, {n_g} GMM Kc=Kd=5 + {n_p} PBAS N=35 independent models "
                                    f"on {S} streams, 8 moving objects + shadows",
                        "H": H, "W": W, "gmm_K": KC, "pbas_N": N_PBAS, "gmm_models": n_g, "pbas_models": n_p,
-                       "streams": S, "live_state_bytes": live, "frames_cycled": F, "parallelism": "single GPU"},
+                       "streams": S, "live_state_bytes": live, **frames_cfg, "parallelism": "single GPU"},
             "roofline": {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                          "traffic": (n_g * tg + n_p * tp) if (tg is not None and tp is not None) else None,
@@ -637,13 +728,9 @@ def main():
                                + ("one launch per kind and step" if batched else "one launch per model and step")
                                + ", 8 moving objects + shadows",
                    "H": H, "W": W, "gmm_K": KC, "pbas_N": N_PBAS, "gmm_models": n_g, "pbas_models": n_p,
-                   "live_state_bytes": live, "frames_cycled": F, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic("pbas_step_1280x720_n35.txt" if dom == "pbas"
-                                                 else "gmm_step_1280x720_k5.txt"),
-                     "kernel": dom + "_step",
-                     "algorithmic_bytes_per_launch": int(p_per * p_b * npx if dom == "pbas" else g_per * g_b * npx)},
+                   "live_state_bytes": live, **frames_cfg, "parallelism": "single GPU"},
+        "roofline": roofline_entry(dom, pbas_ms if dom == "pbas" else gmm_ms, ach,
+                                   p_per if dom == "pbas" else g_per, p_b if dom == "pbas" else g_b),
         "kernels": {k: v for k, v in (
             ("gmm_step", kernel_entry(gmm_ms, g_b, g_gbs, "gmm_step_1280x720_k5.txt", g_launches, g_per, wall / K)),
             ("pbas_step", kernel_entry(pbas_ms, p_b, p_gbs, "pbas_step_1280x720_n35.txt", p_launches, p_per,
@@ -651,10 +738,13 @@ def main():
             if v is not None},
         "copy_probe_GBs": round(copy_gbs, 1),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(rgb_h, dep_h, args.cpu_procs)
     for m, _ in models:
         m.close()
+    del rgb, dep
+    if not args.no_serving:
+        out["serving"] = serving_run(1.0, args.serve_seconds)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(rgb_h, dep_h, args.cpu_procs)
     print(json.dumps(out), flush=True)
 
 

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 1
+#define FGS_ABI_VERSION 4
 
 typedef enum fgs_status {
     FGS_OK = 0,
@@ -124,7 +124,8 @@ typedef struct fgs_gmm_params {
  * Accepted: N in 2..64, min_matches in 1..N, R_lower_j > 0, 0 <= R_incdec < 1,
  * R_scale > 0, 0 < T_lower <= T_upper, T_inc > 0 and T_dec > 0 (T moves by
  * T_inc/d_bar or T_dec/d_bar, +-inf at d_bar = 0 before the clamp; a zero
- * increment would make that 0/0; a fixed update period is T_lower = T_upper).
+ * increment would make that 0/0; a fixed update period is T_lower = T_upper),
+ * gradient 0 or 1, grad_alpha >= 0 and finite.
  */
 typedef struct fgs_pbas_params {
     uint32_t struct_size; /* = sizeof(fgs_pbas_params) */
@@ -134,8 +135,18 @@ typedef struct fgs_pbas_params {
     float T_inc, T_dec, T_lower, T_upper;
     float R_lower[4];     /* per channel R, G, B, depth */
     int32_t depth_max_mm;
-    int32_t reserved0;
+    int32_t gradient;     /* 0: the RGB-D samples of Sec. 3.2 (default).  1: the base
+                             method's gradient-magnitude feature added to the colour
+                             channels (opt-in; the paper's variant leaves it out): m_j =
+                             (|gx| + |gy|) >> 3 of channel j's plane (3x3 Sobel, border
+                             replicated), a sample slot holds (v, m) per colour channel,
+                             dist = w_j * |m - B^m| + |v - B^v| in float32 with
+                             w_j = grad_alpha / max(mean of m_j over the previous frame, 1),
+                             D and S float32; the depth channel as in 0 */
     uint64_t seed;
+    float grad_alpha;     /* gradient weight (default 10; >= 0, finite) */
+    int32_t reserved1;    /* 0 */
+    /* A caller passing the earlier 72-byte struct (no grad_alpha) gets its default. */
 } fgs_pbas_params;
 
 /* ABI version of the loaded library (FGS_ABI_VERSION it was built with). */
@@ -157,7 +168,8 @@ fgs_status fgs_gmm_params_default(fgs_gmm_params* p);
 
 /* Fill *p with the default PBAS constants (Sec. 3.2: N = 20; the rest from the
  * base method: min_matches 2, R_incdec 0.05, R_scale 5, T_inc 1, T_dec 0.05,
- * T in [2, 200], R_lower 18,18,18 and 4 for depth, 10 m full scale).
+ * T in [2, 200], R_lower 18,18,18 and 4 for depth, 10 m full scale; gradient 0,
+ * grad_alpha 10).
  * INVALID_ARG if p is NULL. */
 fgs_status fgs_pbas_params_default(fgs_pbas_params* p);
 
@@ -213,8 +225,9 @@ fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_s
  * rgb[i], rgb_stride[i], depth[i], depth_stride[i], FGS_MEM_DEVICE) for each i.
  * Models of one kind and class share a launch of up to 8 models (GMM: same Kc,
  * Kd, variant and cache policy; PBAS: past its N fill frames, same register class
- * of N and cache policy), so the device ramps up and drains once per launch
- * instead of once per model; other models get launches of their own.
+ * of N and cache policy, not the gradient variant), so the device ramps up and
+ * drains once per launch instead of once per model; other models get launches of
+ * their own.
  *
  * Frames are device memory, each of its model's H x W size (no depth
  * upscaling), rows rgb_stride[i] >= 3W and depth_stride[i] >= 2W (even) bytes
@@ -266,6 +279,29 @@ fgs_status fgs_eval_accumulate(fgs_model* m, const uint8_t* gt, int64_t gt_strid
  * then clears the accumulator.  INVALID_ARG for NULL arguments, DEVICE. */
 fgs_status fgs_eval_read(fgs_model* m, uint64_t counts[4], int32_t reset);
 
+
+/*
+ * Static-object detection on the model's masks.  The paper names the detection of
+ * static objects as future work (Sec. 6) without a method; read here as: a pixel is
+ * part of a static object once the mask has marked it foreground in each of the last M
+ * frames.  Per pixel a run counter c = mask ? min(c + 1, 65535) : 0 is updated after
+ * every push (fgs_push_frame, fgs_push_frame_scaled, fgs_push_frames; a kernel on the
+ * model's stream reading the mask), and the static mask is 255 where c >= M, else 0.
+ * The detector only reads the masks; the background model is not changed by it.
+ *
+ * fgs_static_enable: M in 1..65535 enables the detector (or restarts it with a new M)
+ *   with every counter at 0, from the next push on (allocates 3 bytes per pixel of
+ *   device memory on first use); M = 0 turns it off and frees them.  fgs_set_state
+ *   restarts the counters.  Servers do not run it.  INVALID_ARG for M outside 0..65535,
+ *   OUT_OF_MEMORY, DEVICE.
+ * fgs_static_mask: copy the static mask after the last push (H rows of W bytes, stride
+ *   bytes apart) to host memory (waits) or device memory (stream order).  BAD_STATE if
+ *   the detector is off or has counted no frame yet; INVALID_ARG for NULL, stride < W
+ *   or a bad `where`.
+ */
+fgs_status fgs_static_enable(fgs_model* m, int32_t M);
+fgs_status fgs_static_mask(fgs_model* m, uint8_t* out, int64_t stride, fgs_mem where);
+
 /*
  * Median post-filter of a binary mask.  The paper's method leaves its masks
  * unfiltered (Sec. 3); the base PBAS method it builds on smooths its output with a
@@ -296,13 +332,18 @@ fgs_status fgs_mask_median(const uint8_t* src, int64_t src_stride, uint8_t* dst,
  *     uint32 algo, int32 H, int32 W, int32 A, int32 B, int32 flags,
  *     int64 frames pushed, uint64 seed (PBAS, else 0), 16 bytes reserved.
  *     A,B = Kc,Kd (GMM) or N,0 (PBAS).  flags bit 0: GMM per-channel colour
- *     variances (var_mode 1); every other bit zero.
+ *     variances (var_mode 1); bit 1: PBAS gradient-magnitude samples (gradient 1);
+ *     every other bit zero.
  *   GMM payload (float32 planes of H*W, row-major), in order:
  *     w_c[Kc], mu_c[Kc][3] (R,G,B), v_c[Kc] (v_c[Kc][3] with flags bit 0),
  *     w_d[Kd], mu_d[Kd], v_d[Kd] (each model's Gaussians in rank order).
  *   PBAS payload: samples[N] uint32 planes (bytes R,G,B,depth code),
  *     dhist[N] uint32 planes (bytes D_R, D_G, D_B, D_D), R[4] float32 planes,
  *     T[4] float32 planes, S[4] uint16 planes.
+ *   PBAS payload with flags bit 1: samples[N] uint32 planes, gsamples[N] uint32
+ *     planes (bytes m_R, m_G, m_B, 0), dhist[N][4] float32 planes (slot-major, then
+ *     channel R, G, B, depth), R[4], T[4], S[4] float32 planes, then 3 uint64: the
+ *     colour magnitude sums of the last frame pushed (the next frame's weights).
  * fgs_state_size gives the byte count.  fgs_copy_state first applies any
  * deferred PBAS neighbour writes (so the state is the logical model after the
  * last frame), then copies; FGS_MEM_HOST waits for completion.  fgs_set_state
@@ -324,7 +365,8 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
  *   GMM:  w_c[k], mu_c[k][c], v_c[k] (v_c[k][c] with var_mode 1), w_d[k], mu_d[k],
  *         v_d[k]; float32.
  *   PBAS: samples[k] and dhist[k] uint32 (bytes R,G,B,depth), R[j], T[j] float32,
- *         S[j] uint16.
+ *         S[j] uint16; with gradient 1: samples[k], gsamples[k] uint32, dhist[k][j],
+ *         R[j], T[j], S[j] float32.
  * `name` is a static string naming the array, `index` the rank, slot or channel,
  * `sub` the colour channel of mu_c and per-channel v_c (else 0).
  * With fields == NULL (capacity ignored) the call only writes the number of fields
@@ -395,8 +437,10 @@ fgs_status fgs_set_cache_policy(fgs_model* m, int32_t policy);
  *
  * All arrays are device memory, dense, in the window's stream order:
  * theta float[3]; rgb uint8[T][H][W][3]; depth uint16[T][H][W]; Z float[T][H][W];
- * has_term uint8[T][H][W]; dZ float[T][H][W]; dtheta double[3].  The caller
- * keeps the frames unchanged between forward and backward.  `hip_stream` as in
+ * has_term uint8[T][H][W]; dZ float[T][H][W]; dtheta double[3].  A window holds the
+ * records and checkpoints of its most recent forward only: backward differentiates that
+ * forward, so it must be given the same theta and frames, unchanged since (a caller that
+ * runs several forwards on one window reruns the one it differentiates first).  `hip_stream` as in
  * fgs_create.  Errors: INVALID_ARG, UNSUPPORTED (K, or rho_mode, decision or var_mode
  * != 0: the adjoint is derived for rho = alpha, the Z score and one variance per
  * Gaussian), OUT_OF_MEMORY, BAD_STATE
@@ -419,20 +463,22 @@ fgs_status fgs_gmm_window_destroy(fgs_gmm_window* w);
  * device memory, frames batched continuously: a scheduler thread takes the next
  * queued frame of every stream whose previous frame has finished (at most one
  * frame per stream in flight, so each stream's frames run in order), copies the
- * inputs over, runs ONE kernel launch over all of them (mixed resolutions, GMM
- * and PBAS) and copies the masks back, without waiting for earlier batches; a
- * completion thread stamps each frame's latency.  Per-stream results are exactly
- * those of a model driven alone with fgs_push_frame.
+ * inputs over, runs them on the device and copies the masks back, without waiting
+ * for earlier batches; a completion thread stamps each frame's latency.  Per-stream
+ * results are exactly those of a model driven alone with fgs_push_frame.
+ * Within a batch, GMM streams with Kc = Kd = K (K = 3 or 5, one variance per
+ * Gaussian, any rate or decision variant) and PBAS streams with N <= 40 run in ONE
+ * launch of the serving kernel (mixed resolutions, GMM and PBAS; for the K, whichever
+ * of 3 and 5 has more of the batch's pixels); every other stream runs in the
+ * per-frame step kernels, models of one kernel class sharing a launch of up to 8,
+ * after it on the same stream.
  *
  * fgs_server_create: `hbm_budget_bytes` caps the device memory of all open
  *   streams (models, input slots) plus the server's own buffers; up to
- *   `max_streams` streams; GMM streams must use Kc = Kd = gmm_K (3 or 5), PBAS
- *   streams N <= pbas_N_max (<= 40).  Uses the current device.
- * fgs_server_open: admit a stream (params as in fgs_create).  BUSY when the
- *   budget or the stream slots would be exceeded, also between opens that run
- *   concurrently (nothing stays allocated then);
- *   UNSUPPORTED for a K or N outside the server's classes, or for GMM per-channel
- *   colour variances (var_mode 1); the rate and decision variants are served.
+ *   `max_streams` (1..1024) streams.  Uses the current device.
+ * fgs_server_open: admit a stream with any params fgs_create accepts (errors as
+ *   fgs_create).  BUSY when the budget or the stream slots would be exceeded, also
+ *   between opens that run concurrently (nothing stays allocated then).
  * fgs_server_submit: copy one host frame (dense rgb uint8[H][W][3], depth
  *   uint16[H][W]) into the stream's ring (4 frames) and return a ticket; the
  *   buffers may be reused at once.  t_arrival_s is the frame's arrival on the
@@ -467,8 +513,7 @@ typedef struct fgs_server_stats {
     uint64_t device_bytes_used, device_budget;
 } fgs_server_stats;
 double fgs_server_now(void);
-fgs_status fgs_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32_t gmm_K,
-                             int32_t pbas_N_max, fgs_server** out);
+fgs_status fgs_server_create(size_t hbm_budget_bytes, int32_t max_streams, fgs_server** out);
 fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, const void* params,
                            int32_t* stream_id);
 fgs_status fgs_server_submit(fgs_server* s, int32_t stream_id, const uint8_t* rgb,

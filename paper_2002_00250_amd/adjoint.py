@@ -15,10 +15,12 @@ from . import fgs
 
 
 class GmmWindow:
-    """Device buffers (records, checkpoints, scratch) for T frames of H x W."""
+    """Device buffers (records, checkpoints, scratch) for T frames of H x W.  The records and
+    checkpoints belong to the most recent forward; ``forwards`` counts them."""
 
     def __init__(self, T: int, H: int, W: int, params=None, checkpoint_every: int = 16, device=None):
         self.T, self.H, self.W = T, H, W
+        self.forwards = 0
         self.device = torch.device(device or "cuda")
         self.stream = torch.cuda.Stream(self.device)
         self.handle = fgs.fgs_gmm_window_create(T, H, W, params, checkpoint_every, self.stream.cuda_stream)
@@ -54,6 +56,7 @@ class GmmWindow:
         cur.wait_stream(self.stream)
         for x in (theta, rgb, depth, Z, has):
             x.record_stream(self.stream)
+        self.forwards += 1
         return Z, has
 
     def backward(self, theta: torch.Tensor, rgb: torch.Tensor, depth: torch.Tensor, dZ: torch.Tensor):
@@ -78,17 +81,26 @@ class GmmWindow:
 
 
 class GmmWindowFunction(torch.autograd.Function):
+    """Z, has = apply(theta, rgb, depth, window).  Several applications may share a window
+    (two windows of a sequence in one loss, a probe at another theta): the backward of an
+    application whose records a later forward has overwritten first runs its own forward
+    again on the saved inputs (the same kernels, so the same records), then the adjoint."""
+
     @staticmethod
     def forward(ctx, theta, rgb, depth, window: GmmWindow):
         Z, has = window.forward(theta, rgb, depth)
         ctx.save_for_backward(theta, rgb, depth)
         ctx.window = window
+        ctx.forward_id = window.forwards
         ctx.mark_non_differentiable(has)
         return Z, has
 
     @staticmethod
     def backward(ctx, gZ, ghas):
         theta, rgb, depth = ctx.saved_tensors
+        if ctx.window.forwards != ctx.forward_id:
+            ctx.window.forward(theta, rgb, depth)
+            ctx.forward_id = ctx.window.forwards
         d = ctx.window.backward(theta, rgb, depth, gZ)
         return d.to(theta.dtype), None, None, None
 

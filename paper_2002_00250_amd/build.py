@@ -1,6 +1,9 @@
 """Build libfgs.so for gfx950 with hipcc (in-tree, no JIT cache).
 
     python -m paper_2002_00250_amd.build          # compile every source, link the library
+    python -m paper_2002_00250_amd.build --resource-usage   # the compiler's register,
+                                                  # LDS, scratch and occupancy report of the
+                                                  # step, serving and evaluation kernels
 
 Every HIP source is compiled with -ffp-contract=off (no multiply-add fusion: the
 per-pixel recursions must round each operation separately), default IEEE
@@ -20,7 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfgs.so")
-SOURCES = ["gmm_kernels.hip", "gmm_window.hip", "pbas_kernels.hip", "serve_kernels.hip", "diag_kernels.hip", "eval_kernels.hip", "postfilter_kernels.hip",
+SOURCES = ["gmm_kernels.hip", "gmm_window.hip", "pbas_kernels.hip", "pbas_grad_kernels.hip", "serve_kernels.hip", "diag_kernels.hip", "eval_kernels.hip", "postfilter_kernels.hip", "static_kernels.hip",
            "runtime.cpp", "server.cpp"]
 ARCH = os.environ.get("FGS_OFFLOAD_ARCH", "gfx950")
 
@@ -63,6 +66,58 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# Kernels whose resources the report lists: (source, mangled-name fragment, readable name).
+REPORT_KERNELS = [
+    ("gmm_kernels.hip", "gmm_step_kernelILi8ELi5ELi5ELb1ELb0ELi1E", "gmm_step_kernel<8,5,5,NT,0,1>"),
+    ("gmm_kernels.hip", "gmm_step_kernelILi1ELi5ELi5ELb1ELb0ELi1E", "gmm_step_kernel<1,5,5,NT,0,1>"),
+    ("gmm_kernels.hip", "gmm_step_kernelILi8ELi7ELi3ELb1ELb0ELi1E", "gmm_step_kernel<8,7,3,NT,0,1>"),
+    ("pbas_kernels.hip", "pbas_step_kernelILi8ELi36ELb1E", "pbas_step_kernel<8,36,NT>"),
+    ("pbas_kernels.hip", "pbas_step_kernelILi1ELi20ELb0E", "pbas_step_kernel<1,20,cached>"),
+    ("serve_kernels.hip", "serve_kernelILi5ELi24ELb0E", "serve_kernel<5,24,cached>"),
+    ("serve_kernels.hip", "serve_kernelILi5ELi24ELb1E", "serve_kernel<5,24,NT>"),
+    ("eval_kernels.hip", "eval_count_kernelILb1E", "eval_count_kernel<partials>"),
+    ("postfilter_kernels.hip", "median_mask_kernelILi4ELi16E", "median_mask_kernel<4,16>"),
+]
+FIELDS = ["VGPRs", "AGPRs", "TotalSGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]",
+          "LDS Size [bytes/block]", "VGPRs Spill", "SGPRs Spill"]
+
+
+def resource_usage() -> str:
+    """The compiler's resource-usage remarks (-Rpass-analysis=kernel-resource-usage) for the
+    kernels in REPORT_KERNELS, compiled with the library's own flags, as a text table."""
+    import re
+    import tempfile
+    out = {}
+    with tempfile.TemporaryDirectory() as td:
+        for src in sorted({k[0] for k in REPORT_KERNELS}):
+            cmd = [hipcc()] + common_flags() + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o",
+                                                os.path.join(td, "x.o"), "-Rpass-analysis=kernel-resource-usage"]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compiling {src} failed:\n{r.stderr}")
+            cur = None
+            for line in r.stderr.splitlines():
+                m = re.search(r"remark:\s+Function Name: (\S+)", line)
+                if m:
+                    cur = m.group(1)
+                    out.setdefault(cur, {})
+                    continue
+                m = re.search(r"remark:\s+([^:]+): (\S+) \[-Rpass", line)
+                if m and cur:
+                    out[cur][m.group(1).strip()] = m.group(2)
+    rows = ["kernel | " + " | ".join(FIELDS)]
+    for src, frag, name in REPORT_KERNELS:
+        hits = [k for k in out if frag in k]
+        if not hits:
+            raise RuntimeError(f"no remarks for {name} ({frag}) in {src}")
+        f = out[hits[0]]
+        rows.append(name + " | " + " | ".join(f.get(x, "?") for x in FIELDS))
+    return "\n".join(rows)
+
+
 if __name__ == "__main__":
-    build()
+    if "--resource-usage" in sys.argv[1:]:
+        print(resource_usage())
+    else:
+        build()
     sys.exit(0)

@@ -118,6 +118,7 @@ struct PbasConsts {
     float R_lower[4];
     uint32_t depth_max_mm;
     uint32_t key0, key1;
+    float grad_alpha;  // gradient-magnitude variant only
 };
 
 struct PbasPlanes {
@@ -168,6 +169,51 @@ hipError_t pbas_launch_export(const PbasPlanes& m, int npix, int N, uint8_t* out
 hipError_t pbas_launch_import(const PbasPlanes& m, int npix, int N, const uint8_t* in,
                               hipStream_t s);
 
+// ------------------------------------------- PBAS, gradient magnitudes ----
+// The gradient-magnitude variant (pbas_grad_kernels.hip): slot k of pixel p is word
+// k * npix + p of the plain slot planes `samples` (bytes R, G, B, depth code) and
+// `gsamples` (colour magnitudes m_R, m_G, m_B, 0); D[k * npix + p] holds the four
+// channels' d_min as float4, S their float sums; `last` and `last_g` the pixel's
+// value and magnitudes of the previous frame (pending neighbour writes carry them);
+// gsum[4 * (t mod 3) + j] the sum of frame t's colour magnitudes m_j (frame t adds
+// into its slot, reads frame t-1's and clears frame t+1's).
+struct PbasGradPlanes {
+    uint32_t* samples;
+    uint32_t* gsamples;
+    float4* D;
+    float4* R;
+    float4* T;
+    float4* S;
+    uint32_t* last;
+    uint32_t* last_g;
+    uint8_t* fire[2];
+    uint8_t* mask;
+    unsigned long long* gsum;
+};
+
+struct PbasGradArgs {
+    PbasGradPlanes m;
+    const uint8_t* rgb;
+    const uint8_t* depth;
+    int64_t rgb_stride, depth_stride;
+    int32_t H, W, npix;
+    int32_t depth_h, depth_w;
+    uint32_t t;
+    int32_t apply_pending;
+    PbasConsts c;
+};
+
+hipError_t pbas_grad_launch_init_state(const PbasGradPlanes& m, int npix, const PbasConsts& c, hipStream_t s);
+// One frame: the fill kernel for t < N, else the tile step.
+hipError_t pbas_grad_launch_step(const PbasGradArgs& a, hipStream_t s);
+hipError_t pbas_grad_launch_flush(const PbasGradPlanes& m, int H, int W, uint32_t t_prev, const PbasConsts& c,
+                                  hipStream_t s);
+// Canonical payload (see include/fgs.h) <-> device layout; `t` = frames pushed.
+hipError_t pbas_grad_launch_export(const PbasGradPlanes& m, int npix, int N, int64_t t, uint8_t* out,
+                                   hipStream_t s);
+hipError_t pbas_grad_launch_import(const PbasGradPlanes& m, int npix, int N, int64_t t, const uint8_t* in,
+                                   hipStream_t s);
+
 // ------------------------------------------------------------ serving ----
 // One entry of a serving batch: the next frame of one stream.  GMM entries are
 // cut into 256-pixel tiles, PBAS entries into 64x4 tiles (1-D 256-pixel tiles
@@ -180,7 +226,6 @@ struct ServeEntry {
     GmmStepArgs g;
     PbasStepArgs p;
 };
-bool serve_supported(int gmm_K, int pbas_nmax);
 int serve_pbas_nmax(int N);  // register capacity class of a PBAS model
 // One launch over every tile of every entry (prefix[i] = first tile of entry i,
 // prefix[n] = total), grid-stride over a grid sized to the device.
@@ -195,6 +240,13 @@ constexpr int kEvalSlots = 64;
 hipError_t eval_launch_count(const uint8_t* mask, const uint8_t* gt, int64_t gt_stride, int H, int W,
                              unsigned long long* acc, hipStream_t s);
 hipError_t eval_launch_zero(unsigned long long* acc, hipStream_t s);
+
+// ------------------------------------------------------- static objects ----
+// count[p] = mask[p] ? min(count[p] + 1, 65535) : 0; out[p] = count[p] >= M ? 255 : 0.
+// count and out are 256-byte aligned planes of npix.
+hipError_t static_launch_update(const uint8_t* mask, uint16_t* count, uint8_t* out, int64_t npix, uint32_t M,
+                                hipStream_t s);
+hipError_t static_launch_clear(uint16_t* count, uint8_t* out, int64_t npix, hipStream_t s);
 
 // -------------------------------------------------------- diagnostics ----
 hipError_t diag_launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,

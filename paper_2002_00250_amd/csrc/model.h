@@ -21,6 +21,7 @@ struct fgs_model {
     size_t dev_bytes;
     float4* gmm_state;
     fgs::PbasPlanes pb;
+    fgs::PbasGradPlanes pg;  // PBAS with the gradient-magnitude feature (pp.gradient)
     uint8_t* mask;
     // host-frame staging (allocated on the first host push)
     uint8_t* host_stage;
@@ -33,6 +34,11 @@ struct fgs_model {
     uint8_t* gt_dev;               // its device copy
     hipEvent_t gt_done;
     bool gt_busy;
+    // static-object detection (fgs_static_enable): run counters and the static mask
+    uint16_t* st_count;
+    uint8_t* st_mask;
+    int32_t st_M;       // 0: off
+    int64_t st_frames;  // frames counted since the detector was enabled
     int64_t t;          // frames pushed
     bool pending;       // PBAS: neighbour writes of frame t-1 not yet applied
     bool poisoned;
@@ -57,5 +63,10 @@ void model_next_gmm(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const 
                     int64_t depth_stride, int32_t depth_h, int32_t depth_w, GmmStepArgs* a);
 void model_next_pbas(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
                      int64_t depth_stride, int32_t depth_h, int32_t depth_w, PbasStepArgs* a);
+void model_next_pbas_grad(fgs_model* m, const uint8_t* rgb, int64_t rgb_stride, const uint8_t* depth,
+                          int64_t depth_stride, int32_t depth_h, int32_t depth_w, PbasGradArgs* a);
+// PBAS parameters from a caller's struct (NULL: defaults), honouring struct_size: the
+// current layout, or the earlier one without grad_alpha (which then defaults).
+fgs_status load_pbas_params(const void* src, fgs_pbas_params* out);
 
 }  // namespace fgs

@@ -98,6 +98,7 @@ size_t gmm_payload_bytes(const fgs_model* m) {
 }
 size_t pbas_payload_bytes(const fgs_model* m) {
     const size_t n = (size_t)m->npix;
+    if (m->pp.gradient) return (6 * (size_t)m->pp.N + 12) * n * 4 + 3 * 8;
     return 2 * (size_t)m->pp.N * n * 4 + 8 * n * 4 + 4 * n * 2;
 }
 size_t payload_bytes(const fgs_model* m) {
@@ -129,6 +130,9 @@ fgs_status check_pbas(const fgs_pbas_params& p) {
         return fail(FGS_ERR_INVALID_ARG, "fgs_pbas_params.struct_size %u != %zu", p.struct_size,
                     sizeof(fgs_pbas_params));
     if (p.N < 2 || p.N > 64) return fail(FGS_ERR_INVALID_ARG, "PBAS N = %d not in [2, 64]", p.N);
+    if (p.gradient != 0 && p.gradient != 1) return fail(FGS_ERR_INVALID_ARG, "gradient %d not 0 or 1", p.gradient);
+    if (!(p.grad_alpha >= 0.f && p.grad_alpha < INFINITY) || p.reserved1 != 0)
+        return fail(FGS_ERR_INVALID_ARG, "grad_alpha must be >= 0 and finite, reserved1 0");
     if (p.min_matches < 1 || p.min_matches > p.N)
         return fail(FGS_ERR_INVALID_ARG, "min_matches = %d not in [1, N]", p.min_matches);
     if (!(p.T_lower > 0.f) || !(p.T_upper >= p.T_lower) || !(p.R_scale > 0.f) ||
@@ -174,6 +178,20 @@ fgs_status fgs::load_gmm_params(const void* src, fgs_gmm_params* p) {
     if (size != sizeof(fgs_gmm_params) && size != kV1 && size != kV2 && size != kV3)
         return fail(FGS_ERR_INVALID_ARG, "fgs_gmm_params.struct_size %u is none of %zu, %zu, %zu, %zu", size,
                     sizeof(fgs_gmm_params), kV3, kV2, kV1);
+    std::memcpy(p, src, size);  // the fields it does not cover keep their defaults
+    p->struct_size = sizeof *p;
+    return FGS_OK;
+}
+
+fgs_status fgs::load_pbas_params(const void* src, fgs_pbas_params* p) {
+    fgs_pbas_params_default(p);
+    if (!src) return FGS_OK;
+    constexpr size_t kV1 = offsetof(fgs_pbas_params, grad_alpha);  // the layout before grad_alpha
+    uint32_t size = 0;
+    std::memcpy(&size, src, sizeof size);
+    if (size != sizeof(fgs_pbas_params) && size != kV1)
+        return fail(FGS_ERR_INVALID_ARG, "fgs_pbas_params.struct_size %u is neither %zu nor %zu", size,
+                    sizeof(fgs_pbas_params), kV1);
     std::memcpy(p, src, size);  // the fields it does not cover keep their defaults
     p->struct_size = sizeof *p;
     return FGS_OK;
@@ -235,11 +253,41 @@ void fgs::model_next_pbas(fgs_model* m, const uint8_t* rgb, int64_t rs, const ui
     m->t += 1;
 }
 
+void fgs::model_next_pbas_grad(fgs_model* m, const uint8_t* rgb, int64_t rs, const uint8_t* depth, int64_t ds,
+                               int32_t dh, int32_t dw, PbasGradArgs* a) {
+    a->depth_h = dh;
+    a->depth_w = dw;
+    a->m = m->pg;
+    a->rgb = rgb;
+    a->depth = depth;
+    a->rgb_stride = rs;
+    a->depth_stride = ds;
+    a->H = m->H;
+    a->W = m->W;
+    a->npix = m->npix;
+    a->t = (uint32_t)m->t;
+    a->apply_pending = m->pending ? 1 : 0;
+    a->c = m->pc;
+    m->pending = m->t >= m->pp.N;
+    m->t += 1;
+}
+
 namespace {
+
+// The static-object detector counts the frame just pushed (on the model's stream).
+fgs_status static_after_push(fgs_model* m) {
+    if (m->st_M <= 0) return FGS_OK;
+    FGS_HIP(m, static_launch_update(m->mask, m->st_count, m->st_mask, m->npix, (uint32_t)m->st_M, m->stream));
+    m->st_frames += 1;
+    return FGS_OK;
+}
 
 fgs_status flush_pending(fgs_model* m) {
     if (m->algo != FGS_PBAS || !m->pending) return FGS_OK;
-    FGS_HIP(m, pbas_launch_flush(m->pb, m->H, m->W, (uint32_t)(m->t - 1), m->pc, m->stream));
+    if (m->pp.gradient)
+        FGS_HIP(m, pbas_grad_launch_flush(m->pg, m->H, m->W, (uint32_t)(m->t - 1), m->pc, m->stream));
+    else
+        FGS_HIP(m, pbas_launch_flush(m->pb, m->H, m->W, (uint32_t)(m->t - 1), m->pc, m->stream));
     m->pending = false;
     return FGS_OK;
 }
@@ -305,6 +353,9 @@ fgs_status fgs_pbas_params_default(fgs_pbas_params* p) {
     p->R_lower[3] = 4.0f;
     p->depth_max_mm = 10000;
     p->seed = 0x200200250ull;
+    p->gradient = 0;
+    p->grad_alpha = 10.0f;
+    p->reserved1 = 0;
     return FGS_OK;
 }
 
@@ -329,8 +380,8 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
         st = load_gmm_params(params, &m->gp);
         if (st == FGS_OK) st = check_gmm(m->gp);
     } else {
-        if (params) std::memcpy(&m->pp, params, sizeof m->pp);
-        st = check_pbas(m->pp);
+        st = load_pbas_params(params, &m->pp);
+        if (st == FGS_OK) st = check_pbas(m->pp);
     }
     if (st != FGS_OK) {
         delete m;
@@ -349,6 +400,7 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
     m->pc.depth_max_mm = (uint32_t)m->pp.depth_max_mm;
     m->pc.key0 = (uint32_t)(m->pp.seed & 0xFFFFFFFFu);
     m->pc.key1 = (uint32_t)(m->pp.seed >> 32);
+    m->pc.grad_alpha = m->pp.grad_alpha;
 
     hipError_t e = hipGetDevice(&m->device);
     if (e != hipSuccess) {
@@ -371,9 +423,23 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
     size_t off = 0;
     size_t o_state = 0, o_samples = 0, o_dhist = 0, o_R = 0, o_T = 0, o_S = 0, o_last = 0, o_i0 = 0,
            o_i1 = 0, o_mask = 0;
+    size_t o_gs = 0, o_gsum = 0, o_lastg = 0;
     if (algo == FGS_GMM) {
         o_state = off;
         off += align256((size_t)gmm_planes(m->gp.Kc, m->gp.Kd, m->gp.var_mode) * n * 16);
+    } else if (m->pp.gradient) {
+        const size_t N = (size_t)m->pp.N;
+        o_samples = off; off += align256(N * n * 4);
+        o_gs = off;      off += align256(N * n * 4);
+        o_dhist = off;   off += align256(N * n * 16);
+        o_R = off;       off += align256(n * 16);
+        o_T = off;       off += align256(n * 16);
+        o_S = off;       off += align256(n * 16);
+        o_last = off;    off += align256(n * 4);
+        o_lastg = off;   off += align256(n * 4);
+        o_i0 = off;      off += align256(n);
+        o_i1 = off;      off += align256(n);
+        o_gsum = off;    off += align256(12 * 8);
     } else {
         const size_t N = (size_t)m->pp.N;
         o_samples = off; off += align256((size_t)((N + 3) & ~3) * n * 4);  // quad planes
@@ -398,6 +464,21 @@ fgs_status fgs_create(fgs_algo algo, int32_t H, int32_t W, const void* params, v
     if (algo == FGS_GMM) {
         m->gmm_state = reinterpret_cast<float4*>(m->dev + o_state);
         e = gmm_launch_init(m->gmm_state, m->gp.Kc, m->gp.Kd, m->npix, m->gc, m->stream);
+    } else if (m->pp.gradient) {
+        m->pg.samples = reinterpret_cast<uint32_t*>(m->dev + o_samples);
+        m->pg.gsamples = reinterpret_cast<uint32_t*>(m->dev + o_gs);
+        m->pg.D = reinterpret_cast<float4*>(m->dev + o_dhist);
+        m->pg.R = reinterpret_cast<float4*>(m->dev + o_R);
+        m->pg.T = reinterpret_cast<float4*>(m->dev + o_T);
+        m->pg.S = reinterpret_cast<float4*>(m->dev + o_S);
+        m->pg.last = reinterpret_cast<uint32_t*>(m->dev + o_last);
+        m->pg.last_g = reinterpret_cast<uint32_t*>(m->dev + o_lastg);
+        m->pg.fire[0] = m->dev + o_i0;
+        m->pg.fire[1] = m->dev + o_i1;
+        m->pg.mask = m->mask;
+        m->pg.gsum = reinterpret_cast<unsigned long long*>(m->dev + o_gsum);
+        e = hipMemsetAsync(m->dev, 0, off, m->stream);
+        if (e == hipSuccess) e = pbas_grad_launch_init_state(m->pg, m->npix, m->pc, m->stream);
     } else {
         m->pb.samples = reinterpret_cast<uint32_t*>(m->dev + o_samples);
         m->pb.dhist = reinterpret_cast<uint32_t*>(m->dev + o_dhist);
@@ -434,6 +515,7 @@ fgs_status fgs_destroy(fgs_model* m) {
     if (m->dev) (void)hipFree(m->dev);
     if (m->dev_in) (void)hipFree(m->dev_in);
     if (m->eval_acc) (void)hipFree(m->eval_acc);
+    if (m->st_count) (void)hipFree(m->st_count);
     if (m->gt_dev) (void)hipFree(m->gt_dev);
     if (m->gt_stage) {
         (void)hipEventDestroy(m->gt_done);
@@ -503,12 +585,16 @@ fgs_status fgs_push_frame_scaled(fgs_model* m, const uint8_t* rgb, int64_t rgb_s
         GmmStepArgs a;
         model_next_gmm(m, drgb, rs, ddep, ds, dh, dw, &a);
         FGS_HIP(m, gmm_launch_step(a, m->gp.Kc, m->gp.Kd, m->stream));
+    } else if (m->pp.gradient) {
+        PbasGradArgs a;
+        model_next_pbas_grad(m, drgb, rs, ddep, ds, dh, dw, &a);
+        FGS_HIP(m, pbas_grad_launch_step(a, m->stream));
     } else {
         PbasStepArgs a;
         model_next_pbas(m, drgb, rs, ddep, ds, dh, dw, &a);
         FGS_HIP(m, pbas_launch_step(a, m->stream));
     }
-    return FGS_OK;
+    return static_after_push(m);
 }
 
 fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* const* rgb,
@@ -536,6 +622,7 @@ fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* c
     hipStream_t s = models[0]->stream;
     std::vector<GmmStepArgs> ga(n);
     std::vector<PbasStepArgs> pa(n);
+    std::vector<PbasGradArgs> pg(n);
     std::vector<int> key(n), done(n, 0);
     for (int i = 0; i < n; ++i) {
         fgs_model* m = models[i];
@@ -543,6 +630,9 @@ fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* c
         if (m->algo == FGS_GMM) {
             model_next_gmm(m, rgb[i], rgb_stride[i], d, depth_stride[i], 0, 0, &ga[i]);
             key[i] = gmm_batch_key(ga[i], m->gp.Kc, m->gp.Kd);
+        } else if (m->pp.gradient) {  // launched alone
+            model_next_pbas_grad(m, rgb[i], rgb_stride[i], d, depth_stride[i], 0, 0, &pg[i]);
+            key[i] = -2;
         } else {
             model_next_pbas(m, rgb[i], rgb_stride[i], d, depth_stride[i], 0, 0, &pa[i]);
             key[i] = pbas_batch_key(pa[i]);
@@ -572,6 +662,8 @@ fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* c
             GmmStepArgs b[kBatchMax];
             for (size_t k = 0; k < idx.size(); ++k) b[k] = ga[idx[k]];
             e = gmm_launch_step_batch(b, (int)idx.size(), m->gp.Kc, m->gp.Kd, s);
+        } else if (key[i] == -2) {
+            e = pbas_grad_launch_step(pg[i], s);
         } else if (key[i] < 0) {
             e = pbas_launch_step(pa[i], s);
         } else {
@@ -580,6 +672,10 @@ fgs_status fgs_push_frames(fgs_model* const* models, int32_t n, const uint8_t* c
             e = pbas_launch_step_batch(b, (int)idx.size(), s);
         }
         if (e != hipSuccess) return fail_group(idx, e);
+    }
+    for (int i = 0; i < n; ++i) {
+        const fgs_status st = static_after_push(models[i]);
+        if (st != FGS_OK) return st;
     }
     return FGS_OK;
 }
@@ -599,6 +695,50 @@ fgs_status fgs_get_mask(fgs_model* m, uint8_t* mask, int64_t stride, fgs_mem whe
     } else {
         return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
     }
+    return FGS_OK;
+}
+
+fgs_status fgs_static_enable(fgs_model* m, int32_t M) {
+    if (!m) return fail(FGS_ERR_INVALID_ARG, "model is NULL");
+    if (M < 0 || M > 65535) return fail(FGS_ERR_INVALID_ARG, "M = %d outside 0..65535", M);
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    if (M == 0) {
+        if (m->st_count) {
+            FGS_HIP(m, hipStreamSynchronize(m->stream));
+            (void)hipFree(m->st_count);
+        }
+        m->st_count = nullptr;
+        m->st_mask = nullptr;
+        m->st_M = 0;
+        m->st_frames = 0;
+        return FGS_OK;
+    }
+    const size_t n = (size_t)m->npix;
+    if (!m->st_count) {
+        uint8_t* p = nullptr;
+        hipError_t e = hipMalloc((void**)&p, align256(n * 2) + align256(n));
+        if (e != hipSuccess) return fail(FGS_ERR_OUT_OF_MEMORY, "static-object planes: %s", hipGetErrorString(e));
+        m->st_count = reinterpret_cast<uint16_t*>(p);
+        m->st_mask = p + align256(n * 2);
+    }
+    FGS_HIP(m, static_launch_clear(m->st_count, m->st_mask, m->npix, m->stream));
+    m->st_M = M;
+    m->st_frames = 0;
+    return FGS_OK;
+}
+
+fgs_status fgs_static_mask(fgs_model* m, uint8_t* out, int64_t stride, fgs_mem where) {
+    if (!m || !out) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
+    if (stride < m->W) return fail(FGS_ERR_INVALID_ARG, "mask stride %lld < W", (long long)stride);
+    if (where != FGS_MEM_HOST && where != FGS_MEM_DEVICE)
+        return fail(FGS_ERR_INVALID_ARG, "bad memory kind %d", (int)where);
+    if (m->st_M <= 0) return fail(FGS_ERR_BAD_STATE, "static-object detection is not enabled");
+    if (m->st_frames == 0) return fail(FGS_ERR_BAD_STATE, "no frame has been counted since it was enabled");
+    FGS_HIP(m, hipMemcpy2DAsync(out, (size_t)stride, m->st_mask, (size_t)m->W, (size_t)m->W, (size_t)m->H,
+                                where == FGS_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                m->stream));
+    if (where == FGS_MEM_HOST) FGS_HIP(m, hipStreamSynchronize(m->stream));
     return FGS_OK;
 }
 
@@ -716,7 +856,7 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     h.W = m->W;
     h.A = m->algo == FGS_GMM ? m->gp.Kc : m->pp.N;
     h.B = m->algo == FGS_GMM ? m->gp.Kd : 0;
-    h.flags = m->algo == FGS_GMM ? m->gp.var_mode : 0;
+    h.flags = m->algo == FGS_GMM ? m->gp.var_mode : (m->pp.gradient ? 2 : 0);
     h.frames = m->t;
     h.seed = m->algo == FGS_PBAS ? m->pp.seed : 0;
 
@@ -729,7 +869,8 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     hipError_t e = m->algo == FGS_GMM
                        ? gmm_launch_export(m->gmm_state, reinterpret_cast<float*>(target), m->gp.Kc,
                                            m->gp.Kd, m->gp.var_mode, m->npix, m->stream)
-                       : pbas_launch_export(m->pb, m->npix, m->pp.N, target, m->stream);
+                       : m->pp.gradient ? pbas_grad_launch_export(m->pg, m->npix, m->pp.N, m->t, target, m->stream)
+                                        : pbas_launch_export(m->pb, m->npix, m->pp.N, target, m->stream);
     if (e == hipSuccess) {
         if (where == FGS_MEM_HOST) {
             std::memcpy(dst, &h, sizeof h);
@@ -766,7 +907,7 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
     const int B = m->algo == FGS_GMM ? m->gp.Kd : 0;
     if (h.magic != kStateMagic || h.version != kStateVersion || h.algo != (uint32_t)m->algo ||
         h.H != m->H || h.W != m->W || h.A != A || h.B != B || h.frames < 0 || h.frames >= 0xFFFFFFFFll ||
-        h.flags != (m->algo == FGS_GMM ? m->gp.var_mode : 0))
+        h.flags != (m->algo == FGS_GMM ? m->gp.var_mode : (m->pp.gradient ? 2 : 0)))
         return fail(FGS_ERR_INVALID_ARG, "state header does not match this model");
     if (m->algo == FGS_PBAS && h.seed != m->pp.seed)
         return fail(FGS_ERR_INVALID_ARG, "state was taken with another PBAS seed");
@@ -782,12 +923,18 @@ fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem wh
     if (e == hipSuccess)
         e = m->algo == FGS_GMM ? gmm_launch_import(m->gmm_state, reinterpret_cast<const float*>(srcp),
                                                    m->gp.Kc, m->gp.Kd, m->gp.var_mode, m->npix, m->stream)
-                               : pbas_launch_import(m->pb, m->npix, m->pp.N, srcp, m->stream);
+                               : m->pp.gradient
+                                     ? pbas_grad_launch_import(m->pg, m->npix, m->pp.N, h.frames, srcp, m->stream)
+                                     : pbas_launch_import(m->pb, m->npix, m->pp.N, srcp, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return device_fail(m, e, "set_state");
     m->t = h.frames;
     m->pending = false;
+    if (m->st_M > 0) {  // the detector's runs restart with the new state
+        FGS_HIP(m, static_launch_clear(m->st_count, m->st_mask, m->npix, m->stream));
+        m->st_frames = 0;
+    }
     return FGS_OK;
 }
 
@@ -818,6 +965,21 @@ fgs_status fgs_get_state(fgs_model* m, fgs_state_field* fields, int32_t capacity
         for (int k = 0; k < Kd; ++k) add("w_d", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_wd(Kc, Kd, k)), 16);
         for (int k = 0; k < Kd; ++k) add("mu_d", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_mud(Kc, Kd, k)), 16);
         for (int k = 0; k < Kd; ++k) add("v_d", k, 0, FGS_DTYPE_F32, 4, extra(gmm_x_vd(Kc, Kd, k)), 16);
+    } else if (m->pp.gradient) {
+        const int N = m->pp.N;
+        const uint8_t* smp = reinterpret_cast<const uint8_t*>(m->pg.samples);
+        const uint8_t* gsm = reinterpret_cast<const uint8_t*>(m->pg.gsamples);
+        const uint8_t* dh = reinterpret_cast<const uint8_t*>(m->pg.D);
+        for (int k = 0; k < N; ++k) add("samples", k, 0, FGS_DTYPE_U32, 4, smp + (int64_t)k * n * 4, 4);
+        for (int k = 0; k < N; ++k) add("gsamples", k, 0, FGS_DTYPE_U32, 4, gsm + (int64_t)k * n * 4, 4);
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < 4; ++j) add("dhist", k, j, FGS_DTYPE_F32, 4, dh + (int64_t)k * n * 16 + 4 * j, 16);
+        for (int j = 0; j < 4; ++j)
+            add("R", j, 0, FGS_DTYPE_F32, 4, reinterpret_cast<const uint8_t*>(m->pg.R) + 4 * j, 16);
+        for (int j = 0; j < 4; ++j)
+            add("T", j, 0, FGS_DTYPE_F32, 4, reinterpret_cast<const uint8_t*>(m->pg.T) + 4 * j, 16);
+        for (int j = 0; j < 4; ++j)
+            add("S", j, 0, FGS_DTYPE_F32, 4, reinterpret_cast<const uint8_t*>(m->pg.S) + 4 * j, 16);
     } else {
         const int N = m->pp.N;
         const uint8_t* smp = reinterpret_cast<const uint8_t*>(m->pb.samples);
@@ -864,6 +1026,7 @@ fgs_status fgs_device_bytes(const fgs_model* m, size_t* bytes) {
     if (!m || !bytes) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
     size_t b = m->dev_bytes;
     if (m->dev_in) b += align256((size_t)m->npix * 3) + align256((size_t)m->npix * 2);
+    if (m->st_count) b += align256((size_t)m->npix * 2) + align256((size_t)m->npix);
     *bytes = b;
     return FGS_OK;
 }

@@ -50,10 +50,6 @@ void launch(const ServeEntry* e, const int32_t* prefix, int n, int grid, bool nt
 
 int serve_pbas_nmax(int N) { return N <= 24 ? 24 : (N <= 40 ? 40 : 0); }
 
-bool serve_supported(int gmm_K, int pbas_nmax) {
-    return (gmm_K == 3 || gmm_K == 5) && (pbas_nmax == 24 || pbas_nmax == 40);
-}
-
 hipError_t serve_launch(const ServeEntry* entries, const int32_t* prefix, int n, int total_tiles,
                         int gmm_K, int pbas_nmax, bool streaming, hipStream_t s) {
     if (n <= 0 || total_tiles <= 0) return hipSuccess;

@@ -83,7 +83,7 @@ fgs_status fail(fgs_status s, const char* fmt, A... args) {
 
 struct fgs_server {
     size_t budget = 0, used = 0;
-    int max_streams = 0, gmm_K = 5, pbas_nmax = 24;
+    int max_streams = 0;
     int device = 0;
     hipStream_t compute = nullptr, h2d = nullptr, d2h = nullptr;
     std::mutex mu;
@@ -129,6 +129,66 @@ bool ready(const Stream* st) {
     return !st->closed && !st->inflight && st->slots[st->next_run].state == kQueued;
 }
 
+// Serving classes.  The fused serving kernel runs GMM streams with Kc = Kd = K, K one
+// of {3, 5}, one variance per Gaussian (any rate or decision variant), and PBAS streams
+// with N <= 40, mixed, in ONE launch; its instance is chosen per batch (K: whichever of
+// 3 and 5 has more of the batch's pixels; PBAS register class 24 or 40: the largest N
+// among its PBAS streams).  Every other stream (the other K, any other (Kc, Kd),
+// per-channel variances, N > 40) runs through the per-frame step kernels, grouped by
+// kernel class, up to kBatchMax models per launch, after the fused launch on the same
+// stream.  A stream's results are those of its model pushed alone either way.
+bool fused_gmm(const fgs_model* m) {
+    return m->gp.Kc == m->gp.Kd && (m->gp.Kc == 3 || m->gp.Kc == 5) && m->gp.var_mode == 0;
+}
+bool fused_pbas(const fgs_model* m) { return m->pp.N <= 40 && !m->pp.gradient; }
+
+// Launches of the streams outside the fused kernel's class: models of one kind and
+// batch key share a launch of up to kBatchMax; PBAS fill frames go alone.
+hipError_t launch_other(const std::vector<std::pair<GmmStepArgs, const fgs_model*>>& og,
+                        const std::vector<PbasStepArgs>& op, const std::vector<PbasGradArgs>& opg,
+                        hipStream_t s) {
+    for (const PbasGradArgs& a : opg) {  // the gradient-magnitude variant: one launch each
+        const hipError_t e = pbas_grad_launch_step(a, s);
+        if (e != hipSuccess) return e;
+    }
+    std::vector<char> used(og.size(), 0);
+    for (size_t i = 0; i < og.size(); ++i) {
+        if (used[i]) continue;
+        const fgs_model* mi = og[i].second;
+        const int key = gmm_batch_key(og[i].first, mi->gp.Kc, mi->gp.Kd);
+        GmmStepArgs b[kBatchMax];
+        int n = 0;
+        for (size_t j = i; j < og.size() && n < kBatchMax; ++j) {
+            if (used[j] || gmm_batch_key(og[j].first, og[j].second->gp.Kc, og[j].second->gp.Kd) != key) continue;
+            used[j] = 1;
+            b[n++] = og[j].first;
+        }
+        const hipError_t e = gmm_launch_step_batch(b, n, mi->gp.Kc, mi->gp.Kd, s);
+        if (e != hipSuccess) return e;
+    }
+    std::vector<char> pused(op.size(), 0);
+    for (size_t i = 0; i < op.size(); ++i) {
+        if (pused[i]) continue;
+        const int key = pbas_batch_key(op[i]);
+        if (key < 0) {  // a fill frame
+            pused[i] = 1;
+            const hipError_t e = pbas_launch_step(op[i], s);
+            if (e != hipSuccess) return e;
+            continue;
+        }
+        PbasStepArgs b[kBatchMax];
+        int n = 0;
+        for (size_t j = i; j < op.size() && n < kBatchMax; ++j) {
+            if (pused[j] || pbas_batch_key(op[j]) != key) continue;
+            pused[j] = 1;
+            b[n++] = op[j];
+        }
+        const hipError_t e = pbas_launch_step_batch(b, n, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 // Enqueue one batch on the device (scheduler thread, lock not held).  Only the
 // scheduler touches the models' frame bookkeeping.
 hipError_t issue(fgs_server* s, Batch* b) {
@@ -146,40 +206,80 @@ hipError_t issue(fgs_server* s, Batch* b) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, b->in_done, 0);
     if (e != hipSuccess) return e;
 
+    // the fused kernel's instance for this batch
+    int64_t px3 = 0, px5 = 0;
+    int pbas_n = 0;
+    for (auto& it : b->items) {
+        const fgs_model* m = it.first->model;
+        if (it.first->algo == FGS_GMM && fused_gmm(m)) (m->gp.Kc == 3 ? px3 : px5) += it.first->npix;
+        if (it.first->algo == FGS_PBAS && fused_pbas(m)) pbas_n = std::max(pbas_n, (int)m->pp.N);
+    }
+    const int kg = px5 >= px3 ? 5 : 3;
+    const int np = serve_pbas_nmax(std::max(pbas_n, 2));
+
     ServeEntry* d = s->h_desc[r];
     int32_t* pre = s->h_prefix[r];
-    const int n = (int)b->items.size();
-    int total = 0;
+    int n = 0, total = 0;
     bool streaming = false;
-    for (int i = 0; i < n; ++i) {
-        Stream* st = b->items[i].first;
-        Slot& sl = st->slots[b->items[i].second];
-        ServeEntry& en = d[i];
-        std::memset(&en, 0, sizeof en);
-        en.algo = st->algo;
+    std::vector<std::pair<GmmStepArgs, const fgs_model*>> og;
+    std::vector<PbasStepArgs> op;
+    std::vector<PbasGradArgs> opg;
+    for (auto& it : b->items) {
+        Stream* st = it.first;
+        Slot& sl = st->slots[it.second];
         const uint8_t* drgb = sl.d_in;
         const uint8_t* ddep = sl.d_in + st->rgb_bytes;
+        fgs_model* m = st->model;
         if (st->algo == FGS_GMM) {
-            model_next_gmm(st->model, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &en.g);
+            GmmStepArgs ga;
+            model_next_gmm(m, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &ga);
+            if (!(fused_gmm(m) && m->gp.Kc == kg)) {
+                og.emplace_back(ga, m);
+                continue;
+            }
+            ServeEntry& en = d[n];
+            std::memset(&en, 0, sizeof en);
+            en.algo = FGS_GMM;
+            en.g = ga;
             en.ntiles = (st->npix + 255) / 256;
-            streaming = streaming || en.g.streaming;
+            streaming = streaming || ga.streaming;
+        } else if (m->pp.gradient) {
+            PbasGradArgs pa;
+            model_next_pbas_grad(m, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &pa);
+            opg.push_back(pa);
+            continue;
         } else {
-            en.fill = st->model->t < st->model->pp.N ? 1 : 0;
-            model_next_pbas(st->model, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &en.p);
+            const int fill = m->t < m->pp.N ? 1 : 0;
+            PbasStepArgs pa;
+            model_next_pbas(m, drgb, 3 * (int64_t)st->W, ddep, 2 * (int64_t)st->W, 0, 0, &pa);
+            if (!fused_pbas(m)) {
+                op.push_back(pa);
+                continue;
+            }
+            ServeEntry& en = d[n];
+            std::memset(&en, 0, sizeof en);
+            en.algo = FGS_PBAS;
+            en.fill = fill;
+            en.p = pa;
             en.tiles_x = (st->W + 63) / 64;
-            en.ntiles = en.fill ? (st->npix + 255) / 256 : en.tiles_x * ((st->H + 3) / 4);
-            streaming = streaming || en.p.streaming;
+            en.ntiles = fill ? (st->npix + 255) / 256 : en.tiles_x * ((st->H + 3) / 4);
+            streaming = streaming || pa.streaming;
         }
-        pre[i] = total;
-        total += en.ntiles;
+        pre[n] = total;
+        total += d[n].ntiles;
+        n += 1;
     }
     pre[n] = total;
-    ServeEntry* dd = reinterpret_cast<ServeEntry*>(s->d_ring + r * (s->desc_cap * sizeof(ServeEntry) +
-                                                                   align256((s->desc_cap + 1) * 4)));
-    int32_t* dp = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(dd) + s->desc_cap * sizeof(ServeEntry));
-    e = hipMemcpyAsync(dd, d, n * sizeof(ServeEntry), hipMemcpyHostToDevice, s->compute);
-    if (e == hipSuccess) e = hipMemcpyAsync(dp, pre, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s->compute);
-    if (e == hipSuccess) e = serve_launch(dd, dp, n, total, s->gmm_K, s->pbas_nmax, streaming, s->compute);
+    if (n > 0) {
+        ServeEntry* dd = reinterpret_cast<ServeEntry*>(s->d_ring + r * (s->desc_cap * sizeof(ServeEntry) +
+                                                                       align256((s->desc_cap + 1) * 4)));
+        int32_t* dp = reinterpret_cast<int32_t*>(reinterpret_cast<uint8_t*>(dd) + s->desc_cap * sizeof(ServeEntry));
+        e = hipMemcpyAsync(dd, d, n * sizeof(ServeEntry), hipMemcpyHostToDevice, s->compute);
+        if (e == hipSuccess) e = hipMemcpyAsync(dp, pre, (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s->compute);
+        if (e == hipSuccess) e = serve_launch(dd, dp, n, total, kg, np, streaming, s->compute);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_other(og, op, opg, s->compute);
     if (e == hipSuccess) e = hipEventRecord(s->ring_ev[r], s->compute);
     if (e != hipSuccess) return e;
     s->ring_used[r] = true;
@@ -315,20 +415,15 @@ extern "C" {
 
 double fgs_server_now(void) { return now_s(); }
 
-fgs_status fgs_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32_t gmm_K,
-                             int32_t pbas_N_max, fgs_server** out) {
+fgs_status fgs_server_create(size_t hbm_budget_bytes, int32_t max_streams, fgs_server** out) {
     if (!out) return fail(FGS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    const int nmax = serve_pbas_nmax(pbas_N_max);
-    if (max_streams < 1 || max_streams > 1024 || !serve_supported(gmm_K, nmax))
-        return fail(FGS_ERR_INVALID_ARG, "server needs 1 <= max_streams <= 1024, gmm_K in {3,5}, "
-                                         "pbas_N_max <= 40 (got %d, %d, %d)", max_streams, gmm_K, pbas_N_max);
+    if (max_streams < 1 || max_streams > 1024)
+        return fail(FGS_ERR_INVALID_ARG, "server needs 1 <= max_streams <= 1024 (got %d)", max_streams);
     fgs_server* s = new (std::nothrow) fgs_server();
     if (!s) return fail(FGS_ERR_OUT_OF_MEMORY, "host allocation");
     s->budget = hbm_budget_bytes;
     s->max_streams = max_streams;
-    s->gmm_K = gmm_K;
-    s->pbas_nmax = nmax;
     s->desc_cap = (size_t)max_streams;
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
@@ -357,28 +452,7 @@ fgs_status fgs_server_create(size_t hbm_budget_bytes, int32_t max_streams, int32
 fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, const void* params,
                            int32_t* stream_id) {
     if (!s || !stream_id) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
-    if (algo == FGS_GMM) {
-        fgs_gmm_params p;
-        const fgs_status ls = load_gmm_params(params, &p);
-        if (ls != FGS_OK) return ls;
-        if (p.var_mode != 0)
-            return fail(FGS_ERR_UNSUPPORTED, "the server runs GMM streams with one variance per Gaussian");
-        if (p.Kc != s->gmm_K || p.Kd != s->gmm_K)
-            return fail(FGS_ERR_UNSUPPORTED, "this server runs GMM streams with Kc = Kd = %d", s->gmm_K);
-    } else if (algo == FGS_PBAS) {
-        fgs_pbas_params p;
-        fgs_pbas_params_default(&p);
-        if (params) {
-            uint32_t size = 0;
-            std::memcpy(&size, params, sizeof size);
-            if (size != sizeof p)
-                return fail(FGS_ERR_INVALID_ARG, "fgs_pbas_params.struct_size %u != %zu", size, sizeof p);
-            std::memcpy(&p, params, sizeof p);
-        }
-        if (p.N > s->pbas_nmax) return fail(FGS_ERR_UNSUPPORTED, "this server runs PBAS streams with N <= %d", s->pbas_nmax);
-    } else {
-        return fail(FGS_ERR_INVALID_ARG, "unknown algo %d", (int)algo);
-    }
+    if (algo != FGS_GMM && algo != FGS_PBAS) return fail(FGS_ERR_INVALID_ARG, "unknown algo %d", (int)algo);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if ((int)s->streams.size() + s->opening >= s->max_streams)
@@ -396,7 +470,7 @@ fgs_status fgs_server_open(fgs_server* s, fgs_algo algo, int32_t H, int32_t W, c
     }
     // The serving kernel keeps a PBAS pixel's previous value in its own plane (its one
     // instance serves every N up to the class bound): set before the first frame.
-    if (algo == FGS_PBAS) m->pb.last_in_pad = 0;
+    if (algo == FGS_PBAS && !m->pp.gradient) m->pb.last_in_pad = 0;
     sr->model = m;
     sr->algo = algo;
     sr->H = H;

@@ -31,6 +31,7 @@ FGS_CACHE_AUTO = 0
 FGS_CACHE_KEEP = 1
 FGS_CACHE_STREAM = 2
 STATE_HEADER_BYTES = 64
+ABI_VERSION = 4          # FGS_ABI_VERSION of include/fgs.h this binding is written against
 
 
 class FgsError(RuntimeError):
@@ -54,8 +55,8 @@ class fgs_pbas_params(ctypes.Structure):
                 ("R_incdec", ctypes.c_float), ("R_scale", ctypes.c_float),
                 ("T_inc", ctypes.c_float), ("T_dec", ctypes.c_float),
                 ("T_lower", ctypes.c_float), ("T_upper", ctypes.c_float),
-                ("R_lower", ctypes.c_float * 4), ("depth_max_mm", c_int32), ("reserved0", c_int32),
-                ("seed", c_uint64)]
+                ("R_lower", ctypes.c_float * 4), ("depth_max_mm", c_int32), ("gradient", c_int32),
+                ("seed", c_uint64), ("grad_alpha", ctypes.c_float), ("reserved1", c_int32)]
 
 
 class fgs_server_stats(ctypes.Structure):
@@ -117,7 +118,7 @@ def _load():
         "fgs_gmm_window_records": (S, [c_void_p, c_void_p, c_int32]),
         "fgs_gmm_window_destroy": (S, [c_void_p]),
         "fgs_server_now": (ctypes.c_double, []),
-        "fgs_server_create": (S, [c_size_t, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+        "fgs_server_create": (S, [c_size_t, c_int32, POINTER(c_void_p)]),
         "fgs_server_open": (S, [c_void_p, c_int32, c_int32, c_int32, c_void_p, POINTER(c_int32)]),
         "fgs_server_submit": (S, [c_void_p, c_int32, c_void_p, c_void_p, ctypes.c_double, POINTER(c_uint64)]),
         "fgs_server_wait": (S, [c_void_p, c_uint64, c_void_p, POINTER(ctypes.c_double), c_int32]),
@@ -128,11 +129,16 @@ def _load():
         "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
         "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
         "fgs_mask_median": (S, [c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p]),
+        "fgs_static_enable": (S, [c_void_p, c_int32]),
+        "fgs_static_mask": (S, [c_void_p, c_void_p, c_int64, c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
+    if lib.fgs_abi_version() != ABI_VERSION:
+        raise FgsError(-1, f"{LIB_PATH} has ABI version {lib.fgs_abi_version()}, the binding expects "
+                           f"{ABI_VERSION}: rebuild it (python -m paper_2002_00250_amd.build)")
     _lib = lib
     return lib
 
@@ -240,6 +246,14 @@ def fgs_eval_read(m: int, reset: bool = False) -> tuple:
     return tuple(int(v) for v in out)
 
 
+def fgs_static_enable(m: int, M: int) -> None:
+    _check(_load().fgs_static_enable(c_void_p(m), M))
+
+
+def fgs_static_mask(m: int, out: int, stride: int, where: int) -> None:
+    _check(_load().fgs_static_mask(c_void_p(m), c_void_p(out), stride, where))
+
+
 def fgs_state_size(m: int) -> int:
     out = c_size_t()
     _check(_load().fgs_state_size(c_void_p(m), byref(out)))
@@ -321,9 +335,9 @@ def fgs_server_now() -> float:
     return _load().fgs_server_now()
 
 
-def fgs_server_create(hbm_budget_bytes: int, max_streams: int, gmm_K: int = 5, pbas_N_max: int = 24) -> int:
+def fgs_server_create(hbm_budget_bytes: int, max_streams: int) -> int:
     out = c_void_p()
-    _check(_load().fgs_server_create(hbm_budget_bytes, max_streams, gmm_K, pbas_N_max, byref(out)))
+    _check(_load().fgs_server_create(hbm_budget_bytes, max_streams, byref(out)))
     return out.value
 
 
@@ -435,6 +449,16 @@ def unpack_state(blob: np.ndarray) -> dict:
         out.update(Kc=Kc, Kd=Kd, w_c=take(Kc, (Kc, H, W)), mu_c=take(3 * Kc, (Kc, 3, H, W)),
                    v_c=take(3 * Kc, (Kc, 3, H, W)) if diag else take(Kc, (Kc, H, W)),
                    w_d=take(Kd, (Kd, H, W)), mu_d=take(Kd, (Kd, H, W)), v_d=take(Kd, (Kd, H, W)))
+    elif flags & 2:   # PBAS with gradient-magnitude samples
+        N = A
+        u32 = pay[:2 * N * n * 4].view(np.uint32)
+        out.update(N=N, gradient=True, samples=u32[:N * n].reshape(N, H, W),
+                   gsamples=u32[N * n:].reshape(N, H, W))
+        f = pay[2 * N * n * 4:(6 * N + 12) * n * 4].view(np.float32)
+        out.update(dhist=f[:4 * N * n].reshape(N, 4, H, W), R=f[4 * N * n:(4 * N + 4) * n].reshape(4, H, W),
+                   T=f[(4 * N + 4) * n:(4 * N + 8) * n].reshape(4, H, W),
+                   S=f[(4 * N + 8) * n:(4 * N + 12) * n].reshape(4, H, W))
+        out["gsum"] = pay[(6 * N + 12) * n * 4:].copy().view(np.uint64)
     else:
         N = A
         u32 = pay[:2 * N * n * 4].view(np.uint32)
@@ -451,12 +475,17 @@ def pack_state(st: dict) -> np.ndarray:
     algo = st["algo"]
     A, B = (st["Kc"], st["Kd"]) if algo == FGS_GMM else (st["N"], 0)
     hdr[:12] = np.array([0x53534746, 1, algo], np.uint32).view(np.uint8)
-    flags = 1 if algo == FGS_GMM and np.ndim(st["v_c"]) == 4 else 0
+    flags = (1 if algo == FGS_GMM and np.ndim(st["v_c"]) == 4 else 0) | (2 if st.get("gradient") else 0)
     hdr[12:32] = np.array([st["H"], st["W"], A, B, flags], np.int32).view(np.uint8)
     hdr[32:40] = np.array([st["t"]], np.int64).view(np.uint8)
     hdr[40:48] = np.array([st.get("seed", 0)], np.uint64).view(np.uint8)
     if algo == FGS_GMM:
         parts = [np.asarray(st[k], np.float32).ravel() for k in ("w_c", "mu_c", "v_c", "w_d", "mu_d", "v_d")]
+    elif st.get("gradient"):
+        parts = [np.asarray(st["samples"], np.uint32).ravel(), np.asarray(st["gsamples"], np.uint32).ravel(),
+                 np.asarray(st["dhist"], np.float32).ravel(), np.asarray(st["R"], np.float32).ravel(),
+                 np.asarray(st["T"], np.float32).ravel(), np.asarray(st["S"], np.float32).ravel(),
+                 np.asarray(st["gsum"], np.uint64).ravel()]
     else:
         parts = [np.asarray(st["samples"], np.uint32).ravel(), np.asarray(st["dhist"], np.uint32).ravel(),
                  np.asarray(st["R"], np.float32).ravel(), np.asarray(st["T"], np.float32).ravel(),
@@ -582,6 +611,16 @@ class Model:
             self._model_waits_for_torch()
             fgs_eval_accumulate(self.handle, gt.data_ptr(), gt.stride(0), FGS_MEM_DEVICE)
             self._torch_waits_for_model()
+
+    def static_enable(self, M: int) -> None:
+        """Static-object detection: 255 where the mask was foreground in each of the last
+        M frames (fgs_static_enable; M = 0 turns it off)."""
+        fgs_static_enable(self.handle, M)
+
+    def static_mask_host(self) -> np.ndarray:
+        out = np.empty((self.H, self.W), np.uint8)
+        fgs_static_mask(self.handle, out.ctypes.data, self.W, FGS_MEM_HOST)
+        return out
 
     def eval_read(self, reset: bool = False) -> tuple:
         """(TP, TN, FP, FN) accumulated since creation or the last reset."""

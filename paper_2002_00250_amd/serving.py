@@ -14,9 +14,9 @@ from . import fgs
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: int, max_streams: int = 64, gmm_K: int = 5, pbas_N_max: int = 24):
+    def __init__(self, hbm_budget_bytes: int, max_streams: int = 64):
         fgs.lib()
-        self.handle = fgs.fgs_server_create(hbm_budget_bytes, max_streams, gmm_K, pbas_N_max)
+        self.handle = fgs.fgs_server_create(hbm_budget_bytes, max_streams)
         self.shapes = {}
 
     def open(self, algo: int, H: int, W: int, params=None) -> int:

@@ -22,6 +22,8 @@ drawn:
   the background, depth 600 mm nearer) and optional shadows (the background
   RGB scaled by 0.6 in a copy of each rectangle shifted by (+0.15w, +0.10h),
   depth unchanged, not foreground);
+* optionally, rectangles that stop moving at a given frame and stay (left objects, for
+  static-object detection);
 * per-frame noise: RGB + round(N(0, 3)), depth + round(N(0, 10 mm)) clipped to
   >= 1, then 2 % i.i.d. zero-depth holes (invalid depth, ground truth kept).
 
@@ -56,6 +58,7 @@ class SceneConfig:
     planes_mm: tuple = (1500, 3000)
     camouflage_offset_mm: int = 600
     seed: int = DEFAULT_SEED
+    stop_at: int = -1          # >= 0: the rectangles stop moving at this frame (left objects)
 
     def replace(self, **kw) -> "SceneConfig":
         return dataclasses.replace(self, **kw)
@@ -142,6 +145,8 @@ class Scene:
 
     def _pos(self, o, t):
         H, W = self.cfg.H, self.cfg.W
+        if self.cfg.stop_at >= 0:
+            t = min(t, self.cfg.stop_at)
         x = int(round(_bounce(o["x0"], o["vx"], t, W - o["w"])))
         y = int(round(_bounce(o["y0"], o["vy"], t, H - o["h"])))
         return x, y

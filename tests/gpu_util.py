@@ -48,3 +48,18 @@ def compare_pbas_state(gpu: dict, ref: dict, rtol=1e-4):
         out[k] = int((~rel_close(g, r, rtol)).sum())
         out[k + "_bits"] = int((g.view(np.uint32) != r.view(np.uint32)).sum())
     return out
+
+
+def compare_pbas_grad_state(gpu: dict, ref: dict, rtol=1e-4):
+    """The gradient-magnitude variant: sample words and magnitudes and the magnitude sums
+    exact; D, S, R, T within rtol (and counted where not bit-equal)."""
+    out = {}
+    for k in ("samples", "gsamples", "gsum"):
+        out[k] = int((np.asarray(gpu[k]) != np.asarray(ref[k])).sum())
+    for k in ("dhist", "S", "R", "T"):
+        g = np.asarray(gpu[k], np.float32)
+        r = np.asarray(ref[k], np.float32)
+        assert g.shape == r.shape, (k, g.shape, r.shape)
+        out[k] = int((~rel_close(g, r, rtol)).sum())
+        out[k + "_bits"] = int((g.view(np.uint32) != r.view(np.uint32)).sum())
+    return out

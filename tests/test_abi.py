@@ -36,11 +36,11 @@ def test_binding_covers_header_and_struct_sizes(libfgs):
     for n in declared_functions():
         assert hasattr(fgs, n), n
     assert ctypes.sizeof(fgs.fgs_gmm_params) == 72
-    assert ctypes.sizeof(fgs.fgs_pbas_params) == 72
+    assert ctypes.sizeof(fgs.fgs_pbas_params) == 80
     p = fgs.fgs_gmm_params_default()
     assert p.struct_size == 72 and (p.Kc, p.Kd) == (3, 3) and (p.rho_mode, p.decision, p.var_mode) == (0, 0, 0)
     q = fgs.fgs_pbas_params_default()
-    assert q.struct_size == 72 and q.N == 20 and list(q.R_lower) == [18, 18, 18, 4]
+    assert q.struct_size == 80 and q.N == 20 and list(q.R_lower) == [18, 18, 18, 4]
 
 
 def test_defaults_match_oracle_readings(libfgs):
@@ -57,7 +57,7 @@ def test_defaults_match_oracle_readings(libfgs):
         assert np.float32(getattr(g, a)) == np.float32(getattr(og, b)), a
     q, oq = fgs.fgs_pbas_params_default(), PbasParams()
     for a in ("N", "min_matches", "R_incdec", "R_scale", "T_inc", "T_dec", "T_lower", "T_upper",
-              "depth_max_mm", "seed"):
+              "depth_max_mm", "seed", "gradient", "grad_alpha"):
         assert np.float64(getattr(q, a)) == np.float64(np.float32(getattr(oq, a))) or \
             getattr(q, a) == getattr(oq, a), a
 

@@ -113,6 +113,36 @@ def test_window_gradient_end_to_end_matches_fp64_reference(E):
     win.close()
 
 
+def test_two_applications_on_one_window():
+    # Two forwards on one window before the backward (two thetas in one loss): each
+    # gradient is that of its own forward, against the fp64 reference at its theta.
+    from paper_2002_00250_amd.adjoint import GmmWindow, GmmWindowFunction, window_bce_loss
+    p = GmmParams(Kc=3, Kd=3)
+    H, W, T = 24, 40, 40
+    rgb, dep, gt = Scene(preset("adjoint_640x480", H=H, W=W)).frames(0, T)
+    thetas = [(0.01, 2.5, 1.0), (0.03, 2.0, 0.5)]
+    refs = [_oracle_grad(rgb, dep, gt, p, th)[2] for th in thetas]
+    win = GmmWindow(T, H, W, _params_c(p), checkpoint_every=16)
+    r, d, g = _dev(rgb, dep, gt)
+    ts = [torch.tensor(th, dtype=torch.float32, device="cuda", requires_grad=True) for th in thetas]
+    losses = [window_bce_loss(*GmmWindowFunction.apply(t, r, d, win), g) for t in ts]
+    assert win.forwards == 2
+    (losses[0] + losses[1]).backward()
+    for t, g_ref, th in zip(ts, refs, thetas):
+        gg = t.grad.double().cpu().numpy()
+        rel = np.abs(gg - g_ref) / np.abs(g_ref)
+        log(f"two applications on one window, theta {th}: grad gpu {gg} ref {g_ref} rel {rel}")
+        assert np.all(rel <= 1e-3)
+    # backward of the first application alone, after the second one's forward
+    ts = [torch.tensor(th, dtype=torch.float32, device="cuda", requires_grad=True) for th in thetas]
+    first = window_bce_loss(*GmmWindowFunction.apply(ts[0], r, d, win), g)
+    window_bce_loss(*GmmWindowFunction.apply(ts[1], r, d, win), g)
+    first.backward()
+    rel = np.abs(ts[0].grad.double().cpu().numpy() - refs[0]) / np.abs(refs[0])
+    assert np.all(rel <= 1e-3), rel
+    win.close()
+
+
 def test_window_gradient_through_the_variance_floor():
     # a fast rate puts the variances on their floors inside the window: the clamped steps'
     # adjoints must vanish on the GPU as in the fp64 reference

@@ -48,6 +48,7 @@ def _pbas_params_c(p: PbasParams):
     for j in range(4):
         c.R_lower[j] = p.R_lower[j]
     c.depth_max_mm, c.seed = p.depth_max_mm, p.seed
+    c.gradient, c.grad_alpha = int(p.gradient), p.grad_alpha
     return c
 
 

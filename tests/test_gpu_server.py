@@ -50,8 +50,8 @@ def _oracle_params(algo, p):
     library's defaults are the oracle's; only the fields these tests change are copied)."""
     from paper_2002_00250_amd import fgs
     if algo == fgs.FGS_GMM:
-        return GmmParams(Kc=p.Kc, Kd=p.Kd, rho_mode=p.rho_mode, decision=p.decision)
-    return PbasParams(N=p.N, seed=p.seed)
+        return GmmParams(Kc=p.Kc, Kd=p.Kd, rho_mode=p.rho_mode, decision=p.decision, var_mode=p.var_mode)
+    return PbasParams(N=p.N, seed=p.seed, gradient=bool(p.gradient), grad_alpha=p.grad_alpha)
 
 
 def _oracle(algo, H, W, params, frames):
@@ -81,7 +81,7 @@ def test_mix_equals_alone(gmm_variant):
              (fgs.FGS_PBAS, 70, 100), (fgs.FGS_GMM, 120, 160), (fgs.FGS_PBAS, 121, 159),
              (fgs.FGS_PBAS, 5, 7)]
     T = 36
-    srv = Server(1 << 30, 16, gmm_K=5, pbas_N_max=24)
+    srv = Server(1 << 30, 16)
     streams = []
     for i, (algo, H, W) in enumerate(specs):
         p = _params(algo, seed=1000 + i, gmm_variant=gmm_variant)
@@ -121,7 +121,7 @@ def test_pbas_n_up_to_40_in_the_mix_equals_alone():
     # slots: N = 35 (one padding slot) and N = 5 next to each other in one launch
     from paper_2002_00250_amd import fgs
     from paper_2002_00250_amd.serving import Server
-    srv = Server(1 << 30, 8, gmm_K=3, pbas_N_max=40)
+    srv = Server(1 << 30, 8)
     specs = [(fgs.FGS_PBAS, 70, 100, 35), (fgs.FGS_PBAS, 33, 47, 5), (fgs.FGS_GMM, 40, 64, 0)]
     T = 45
     streams = []
@@ -149,7 +149,7 @@ def test_pbas_n_up_to_40_in_the_mix_equals_alone():
 def test_admission_by_budget_and_close():
     from paper_2002_00250_amd import fgs
     from paper_2002_00250_amd.serving import Server
-    srv = Server(64 << 20, 8, gmm_K=5, pbas_N_max=24)
+    srv = Server(64 << 20, 8)
     ids = []
     with pytest.raises(fgs.FgsError) as e:
         for _ in range(10):
@@ -160,14 +160,67 @@ def test_admission_by_budget_and_close():
     srv.close_stream(ids[0])
     assert srv.stats()["device_bytes_used"] < used
     ids[0] = srv.open(fgs.FGS_GMM, 240, 320, _params(fgs.FGS_GMM))   # admitted again
+    bad = _params(fgs.FGS_GMM)
+    bad.Kc, bad.Kd = 4, 2                                           # no such model
     with pytest.raises(fgs.FgsError) as e:
-        srv.open(fgs.FGS_GMM, 24, 32, _params(fgs.FGS_GMM, K=3))     # wrong K class
-    assert e.value.status == fgs.FGS_ERR_UNSUPPORTED
-    pv = _params(fgs.FGS_GMM)
-    pv.var_mode = 1                                                 # per-channel variances
-    with pytest.raises(fgs.FgsError) as e:
-        srv.open(fgs.FGS_GMM, 24, 32, pv)
-    assert e.value.status == fgs.FGS_ERR_UNSUPPORTED
+        srv.open(fgs.FGS_GMM, 24, 32, bad)
+    assert e.value.status == fgs.FGS_ERR_INVALID_ARG
+    srv.destroy()
+
+
+def test_every_stream_class_in_one_server():
+    # One server, streams of every kernel class: GMM K = 5 and K = 3 (both eligible for the
+    # fused serving launch; the one with fewer pixels runs in the step kernels), the
+    # paper's 7/3, K = 1, per-channel variances, the rate and decision variants; PBAS
+    # N = 20 and 35 (fused), 50 and 64 (step kernels), 5, and the gradient-magnitude
+    # variant (a launch of its own).  Uneven arrivals make batches
+    # of changing make-up.  Every stream equals the oracle and the stream alone.
+    from paper_2002_00250_amd import fgs
+    from paper_2002_00250_amd.serving import Server
+    G, P = fgs.FGS_GMM, fgs.FGS_PBAS
+    specs = [(G, 40, 64, dict(K=(5, 5))), (G, 33, 47, dict(K=(3, 3))), (G, 30, 70, dict(K=(7, 3))),
+             (G, 21, 37, dict(K=(1, 1))), (G, 45, 60, dict(K=(5, 5), var_mode=1)),
+             (G, 28, 50, dict(K=(3, 3), rho_mode=2, decision=1)), (G, 64, 80, dict(K=(5, 5), rho_mode=1)),
+             (P, 36, 70, dict(N=20)), (P, 29, 66, dict(N=35)), (P, 24, 40, dict(N=50)),
+             (P, 17, 65, dict(N=64)), (P, 9, 10, dict(N=5)), (P, 23, 45, dict(N=10, gradient=1))]
+    T = 72
+    srv = Server(1 << 30, 16)
+    streams = []
+    for i, (algo, H, W, o) in enumerate(specs):
+        if algo == G:
+            p = fgs.fgs_gmm_params_default()
+            p.Kc, p.Kd = o["K"]
+            p.var_mode, p.rho_mode, p.decision = o.get("var_mode", 0), o.get("rho_mode", 0), o.get("decision", 0)
+        else:
+            p = fgs.fgs_pbas_params_default()
+            p.N, p.seed, p.gradient = o["N"], 4000 + i, o.get("gradient", 0)
+        streams.append((srv.open(algo, H, W, p), algo, H, W, p, _frames(H, W, T, seed=500 + i)))
+    got = {sid: [] for sid, *_ in streams}
+    for t in range(T):
+        late = [st for st in streams if (t * 7 + st[0]) % 4 == 0 and t > 0]
+        tickets = [(sid, srv.submit(sid, *fr[t]), H, W) for sid, algo, H, W, p, fr in streams
+                   if not ((t * 7 + sid) % 4 == 0 and t > 0)]
+        for sid, tk, H, W in tickets:
+            m = np.empty((H, W), np.uint8)
+            srv.wait(tk, m)
+            got[sid].append(m)
+        for sid, algo, H, W, p, fr in late:
+            m = np.empty((H, W), np.uint8)
+            srv.wait(srv.submit(sid, *fr[t]), m)
+            got[sid].append(m)
+    st = srv.stats()
+    log(f"every class: {st['frames_done']} frames in {st['batches']} batches")
+    for sid, algo, H, W, p, fr in streams:
+        orc = _oracle(algo, H, W, p, fr)
+        ref = _alone(algo, H, W, p, fr)
+        odiff = sum(int((a != b).sum()) for a, b in zip(got[sid], orc))
+        diff = sum(int((a != b).sum()) for a, b in zip(got[sid], ref))
+        what = (f"GMM {p.Kc}/{p.Kd} var {p.var_mode} rho {p.rho_mode} dec {p.decision}" if algo == G
+                else f"PBAS N={p.N}" + (" gradient" if p.gradient else ""))
+        fg = sum(int((m != 0).sum()) for m in got[sid])
+        log(f"stream {sid} ({what}, {H}x{W}): {odiff} mask pixels differ from the oracle, {diff} from alone "
+            f"({fg} foreground pixel-frames)")
+        assert len(got[sid]) == T and odiff == 0 and diff == 0
     srv.destroy()
 
 
@@ -341,7 +394,7 @@ def test_32_streams_30fps_mixed_resolution():
     from paper_2002_00250_amd import fgs
     from paper_2002_00250_amd.serving import Server, StreamLoad, run_camera_load
     sizes = [(240, 424)] * 12 + [(480, 640)] * 12 + [(720, 1280)] * 8
-    srv = Server(64 << 30, 32, gmm_K=5, pbas_N_max=24)
+    srv = Server(64 << 30, 32)
     loads, meta = [], []
     for i, (H, W) in enumerate(sizes):
         algo = fgs.FGS_GMM if i % 2 == 0 else fgs.FGS_PBAS
