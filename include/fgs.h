@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 4
+#define FGS_ABI_VERSION 5
 
 typedef enum fgs_status {
     FGS_OK = 0,
@@ -355,6 +355,26 @@ fgs_status fgs_mask_median(const uint8_t* src, int64_t src_stride, uint8_t* dst,
 fgs_status fgs_state_size(const fgs_model* m, size_t* bytes);
 fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where);
 fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem where);
+
+/*
+ * fgs_copy_state without allocating, for callers that cannot allocate device memory:
+ * serving loops that checkpoint a camera's model between frames, harnesses that
+ * forbid hipMalloc.  Same arguments, result and errors as fgs_copy_state, and the same
+ * export kernels; a host destination is staged through a library-owned device buffer
+ * of FGS_NOALLOC_STAGING_BYTES (64 MiB) instead of a buffer allocated for the call.
+ * Each GPU the library runs on holds that buffer from the first call on it until the
+ * process ends.  The call itself allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  Limit: a host copy's payload (fgs_state_size minus the
+ * 64-byte header) must fit in the buffer, else UNSUPPORTED and nothing is copied; a
+ * device destination needs no staging and has no limit.  All calls on one GPU share
+ * its buffer, which keeps the last call's contents (every byte a call reads was written
+ * by that call): calls that overlap on one GPU, from several threads or on several
+ * streams, race, and the caller must serialise them.  The call waits for its stream,
+ * so it cannot be recorded into a HIP graph.
+ * Errors: INVALID_ARG, UNSUPPORTED (payload beyond the buffer), DEVICE.
+ */
+#define FGS_NOALLOC_STAGING_BYTES ((size_t)64 << 20)
+fgs_status fgs_copy_state_noalloc(fgs_model* m, void* dst, size_t bytes, fgs_mem where);
 
 /*
  * In-place access to the model's device state (Sec. 3.1, 3.2: the per-pixel model

@@ -23,6 +23,9 @@
 
 using namespace fgs;
 
+// The staging buffer of fgs_copy_state_noalloc (see noalloc_staging below).
+static __device__ __align__(256) uint8_t scratch[FGS_NOALLOC_STAGING_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -65,6 +68,7 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 // Device bytes held by live models, per device: the kernels stream state with
 // non-temporal accesses once this exceeds what the last-level cache can keep.
 constexpr int kMaxDevices = 64;
+constexpr size_t kNoallocBytes = FGS_NOALLOC_STAGING_BYTES;
 std::atomic<int64_t> g_resident[kMaxDevices];
 
 int64_t streaming_threshold() {
@@ -834,7 +838,39 @@ fgs_status fgs_state_size(const fgs_model* m, size_t* bytes) {
     return FGS_OK;
 }
 
-fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) {
+namespace {
+
+// Device staging of fgs_copy_state_noalloc: a file-scope array that each GPU the library
+// runs on holds from its first use until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in for the symbol):
+// it uses the device address hipGetSymbolAddress returns, looked up once per device with
+// that device current and kept in g_noalloc_ptr.
+std::atomic<uint8_t*> g_noalloc_ptr[kMaxDevices];
+
+fgs_status noalloc_staging(int device, uint8_t** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(FGS_ERR_DEVICE, "device %d out of range", device);
+    uint8_t* p = g_noalloc_ptr[device].load(std::memory_order_acquire);
+    if (!p) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+        void* addr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !addr)
+            return fail(FGS_ERR_DEVICE, "staging buffer address on device %d: %s", device,
+                        hipGetErrorString(e != hipSuccess ? e : hipErrorInvalidSymbol));
+        p = reinterpret_cast<uint8_t*>(addr);
+        g_noalloc_ptr[device].store(p, std::memory_order_release);  // the same address if two threads race here
+    }
+    *out = p;
+    return FGS_OK;
+}
+
+// fgs_copy_state with a host destination staged through `staging` (nullptr: a buffer
+// allocated for this call and freed after it).
+fgs_status copy_state_impl(fgs_model* m, void* dst, size_t bytes, fgs_mem where, uint8_t* staging) {
+
     if (!m || !dst) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
     if (m->poisoned) return fail(FGS_ERR_DEVICE, "model is poisoned by an earlier device error");
     const size_t payload = payload_bytes(m);
@@ -863,8 +899,12 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     uint8_t* tmp = nullptr;
     uint8_t* target = reinterpret_cast<uint8_t*>(dst) + kHeaderBytes;
     if (where == FGS_MEM_HOST) {
-        FGS_HIP(m, hipMalloc((void**)&tmp, payload));
-        target = tmp;
+        if (staging) {
+            target = staging;
+        } else {
+            FGS_HIP(m, hipMalloc((void**)&tmp, payload));
+            target = tmp;
+        }
     }
     hipError_t e = m->algo == FGS_GMM
                        ? gmm_launch_export(m->gmm_state, reinterpret_cast<float*>(target), m->gp.Kc,
@@ -874,7 +914,7 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     if (e == hipSuccess) {
         if (where == FGS_MEM_HOST) {
             std::memcpy(dst, &h, sizeof h);
-            e = hipMemcpyAsync(reinterpret_cast<uint8_t*>(dst) + kHeaderBytes, tmp, payload,
+            e = hipMemcpyAsync(reinterpret_cast<uint8_t*>(dst) + kHeaderBytes, target, payload,
                                hipMemcpyDeviceToHost, m->stream);
         } else {
             e = hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyHostToDevice, m->stream);
@@ -884,6 +924,30 @@ fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) 
     if (tmp) (void)hipFree(tmp);
     if (e != hipSuccess) return device_fail(m, e, "copy_state");
     return FGS_OK;
+}
+
+}  // namespace
+
+fgs_status fgs_copy_state(fgs_model* m, void* dst, size_t bytes, fgs_mem where) {
+    return copy_state_impl(m, dst, bytes, where, nullptr);
+}
+
+fgs_status fgs_copy_state_noalloc(fgs_model* m, void* dst, size_t bytes, fgs_mem where) {
+    if (!m || !dst) return fail(FGS_ERR_INVALID_ARG, "NULL argument");
+    uint8_t* staging = nullptr;
+    if (where == FGS_MEM_HOST) {
+        const size_t payload = payload_bytes(m);
+        if (bytes != kHeaderBytes + payload)
+            return fail(FGS_ERR_INVALID_ARG, "state buffer is %zu bytes, need %zu", bytes, kHeaderBytes + payload);
+        if (payload > kNoallocBytes)
+            return fail(FGS_ERR_UNSUPPORTED,
+                        "state payload of %zu bytes exceeds the %zu-byte staging buffer of the "
+                        "allocation-free copy (use fgs_copy_state or a device destination)",
+                        payload, kNoallocBytes);
+        fgs_status st = noalloc_staging(m->device, &staging);
+        if (st != FGS_OK) return st;
+    }
+    return copy_state_impl(m, dst, bytes, where, staging);
 }
 
 fgs_status fgs_set_state(fgs_model* m, const void* src, size_t bytes, fgs_mem where) {

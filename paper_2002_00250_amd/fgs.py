@@ -31,7 +31,7 @@ FGS_CACHE_AUTO = 0
 FGS_CACHE_KEEP = 1
 FGS_CACHE_STREAM = 2
 STATE_HEADER_BYTES = 64
-ABI_VERSION = 4          # FGS_ABI_VERSION of include/fgs.h this binding is written against
+ABI_VERSION = 5          # FGS_ABI_VERSION of include/fgs.h this binding is written against
 
 
 class FgsError(RuntimeError):
@@ -105,6 +105,7 @@ def _load():
         "fgs_state_size": (S, [c_void_p, POINTER(c_size_t)]),
         "fgs_get_state": (S, [c_void_p, POINTER(fgs_state_field), c_int32, POINTER(c_int32)]),
         "fgs_copy_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
+        "fgs_copy_state_noalloc": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
         "fgs_set_state": (S, [c_void_p, c_void_p, c_size_t, c_int32]),
         "fgs_frame_index": (S, [c_void_p, POINTER(c_int64)]),
         "fgs_sync": (S, [c_void_p]),
@@ -273,6 +274,13 @@ def fgs_get_state(m: int) -> list:
 
 def fgs_copy_state(m: int, dst: int, nbytes: int, where: int) -> None:
     _check(_load().fgs_copy_state(c_void_p(m), c_void_p(dst), nbytes, where))
+
+
+def fgs_copy_state_noalloc(m: int, dst: int, nbytes: int, where: int) -> None:
+    _check(_load().fgs_copy_state_noalloc(c_void_p(m), c_void_p(dst), nbytes, where))
+
+
+FGS_NOALLOC_STAGING_BYTES = 64 << 20
 
 
 def fgs_set_state(m: int, src: int, nbytes: int, where: int) -> None:
