@@ -41,6 +41,67 @@ def pbas_bytes_per_px(N=N_PBAS):
     return 4 * N + 2 * (16 + 16 + 8) + 6
 
 
+def pbas_static_floor_bytes_per_px(N=N_PBAS, T=2.0, channels=4, gran=64, write_gran=None, H=H, W=W):
+    """Expected HBM bytes per pixel-frame that the PBAS step must move at `gran`-byte
+    sectors on a static background, where every pixel is background and T sits at its
+    lower bound, so each channel self-updates and fires into a neighbour with
+    probability u = 1/T, each at a uniform slot among N (the per-channel draws of the
+    method).  State layout of the step kernel: sample quads of 16 B per pixel (4 pixels
+    per 64-byte sector), D history one 4-byte word per slot and pixel (16 pixels per
+    sector).  Counted: every sample quad, R, T, S, input and the fire bytes with their
+    tile halo read; the D-history sectors holding a self-update's old byte read; the
+    sample-quad sectors a self-update or an incoming neighbour write lands in written,
+    with the quad holding the previous-value slot (N >= 33 not a multiple of 4, else a
+    plane of its own); mask and fire bytes written.  Left out, as data-dependent: D, S,
+    R and T writes (on a static background R and T do not move; D and S move only where
+    d_min differs from the byte it replaces).  Reads are counted in `gran`-byte sectors,
+    writes in `write_gran`-byte ones (default: the same)."""
+    wg = write_gran or gran
+    u = 1.0 / T
+    pad = N >= 33 and N % 4 != 0
+    nq = (N + 3) // 4
+    dpx, qpx = gran // 4, wg // 16
+    # a pixel reads D slot k if one of its channels self-updates into slot k
+    p_px = 1.0 - (1.0 - u / N) ** channels
+    d_read = 4.0 * N * (1.0 - (1.0 - p_px) ** dpx)
+    # writes landing in a sector of qpx pixels: self (qpx*C Bernoulli(u)) and incoming
+    # (each of the 8 neighbours of each pixel-channel fires toward it with u/8)
+    s_write = 0.0
+    for q in range(nq):
+        slots = min(4, N - 4 * q)
+        if pad and 4 * q <= N < 4 * q + 4:
+            s_write += 16.0
+            continue
+        z = 1.0 - slots / N
+        clean = (1.0 - u + u * z) ** (qpx * channels) * (1.0 - u / 8 + u / 8 * z) ** (8 * qpx * channels)
+        s_write += 16.0 * (1.0 - clean)
+    tiles_halo = ((64 + 2) * (4 + 2)) / (64 * 4)
+    reads = 16.0 * nq + (0 if pad else 4) + 40.0 + 5.0 + tiles_halo + d_read
+    writes = s_write + (0 if pad else 4) + 2.0
+    return {"total": reads + writes, "D_read": d_read, "samples_write": s_write + (0 if pad else 4),
+            "reads": reads, "writes": writes}
+
+
+PBAS_FLOOR_FILE = "pbas_traffic_floor_1280x720_n35.txt"
+
+
+def pbas_floor_entry():
+    """The PBAS traffic floor: counted from the oracle's run of the benchmark sequence
+    (profiles/pbas_traffic_floor_1280x720_n35.txt, reads in 128-byte lines and writes in
+    64-byte sectors, as the device requests them), and the closed form for a static
+    background with T at its lower bound at the same granularities."""
+    out = {}
+    path = os.path.join(ROOT, "profiles", PBAS_FLOOR_FILE)
+    if os.path.exists(path):
+        kv = _kv(path)
+        if "floor_bytes_per_px" in kv:
+            out["floor_bytes_per_px"] = float(kv["floor_bytes_per_px"])
+            out["floor_source"] = "profiles/" + PBAS_FLOOR_FILE
+    st = pbas_static_floor_bytes_per_px(gran=128, write_gran=64)
+    out["floor_static_T_lower_bytes_per_px"] = round(st["total"], 1)
+    return out
+
+
 def kernel_entry(avg_ms, bytes_per_px, gbs, profile, launches_per_step, models_per_launch, step_s):
     """Per-kernel figures of the default benchmark (None if the kernel did not run)."""
     if not launches_per_step:
@@ -55,6 +116,8 @@ def kernel_entry(avg_ms, bytes_per_px, gbs, profile, launches_per_step, models_p
     if traffic is not None:
         out["GBs_from_traffic"] = round(traffic / (avg_ms * 1e-3) / 1e9, 1)
         out["traffic_bytes_per_px"] = round(traffic / (models_per_launch * H * W), 1)
+    if profile == PROFILE_FILES["pbas"]:
+        out.update(pbas_floor_entry())
     return out
 
 
@@ -64,9 +127,9 @@ PROFILE_FILES = {"gmm": "gmm_step_1280x720_k5.txt", "pbas": "pbas_step_1280x720_
 def roofline_entry(kind, avg_ms, achieved_gbs, models_per_launch, bytes_per_px):
     """The roofline object of the dominant kernel.  achieved / frac count algorithmic bytes
     (the method's state read and written once, input and mask) per launch over the launch's
-    average duration; traffic is the HBM bytes per launch rocprofv3 measured (FETCH_SIZE +
-    WRITE_SIZE, each scaled by what it reads for a plain copy), and *_from_traffic put those
-    bytes over the same duration."""
+    average duration; traffic is the HBM bytes per launch rocprofv3 measured (read requests
+    of 32, 64 and 128 bytes, and WRITE_SIZE), and *_from_traffic put those bytes over the
+    same duration."""
     npx = H * W
     traffic = measured_traffic(PROFILE_FILES[kind])
     out = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -77,10 +140,12 @@ def roofline_entry(kind, avg_ms, achieved_gbs, models_per_launch, bytes_per_px):
         tg = traffic / (avg_ms * 1e-3) / 1e9
         out.update(traffic_bytes_per_px=round(traffic / (models_per_launch * npx), 1),
                    achieved_from_traffic=round(tg, 1), frac_from_traffic=round(tg / HBM_PEAK_GBS, 4))
+    if kind == "pbas":
+        out.update(pbas_floor_entry())
     out["note"] = ("achieved and frac: algorithmic bytes per launch / average launch time (HIP events on the "
-                   "launch stream); traffic: measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                   "profiles/" + PROFILE_FILES[kind] + "), achieved_from_traffic and frac_from_traffic: those "
-                   "bytes over the same time")
+                   "launch stream); traffic: measured HBM bytes per launch (rocprofv3: read requests by size "
+                   "plus WRITE_SIZE, profiles/" + PROFILE_FILES[kind] + "), achieved_from_traffic and "
+                   "frac_from_traffic: those bytes over the same time")
     return out
 
 
@@ -522,7 +587,187 @@ def table1_main(args):
     print(json.dumps(out), flush=True)
 
 
+PROFILE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 {opts} --output-format csv -d $OUT/{sub} -o {name} -- "
+               "python3 $REPO/bench.py --steps 200 --no-cpu-baseline --no-serving")
+PROFILE_PASSES = {  # sub-directory: rocprofv3 options (each --pmc pass in a run of its own)
+    "stats": "--kernel-trace --stats",
+    "pmc_FETCH_SIZE": "--pmc FETCH_SIZE",
+    "pmc_WRITE_SIZE": "--pmc WRITE_SIZE",
+    "pmc_rdreq": "--pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_128B_sum",
+    "pmc_wrreq": "--pmc TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum",
+    "pmc_sq": "--pmc SQ_ACTIVE_INST_VALU SQ_INSTS_VALU SQ_WAVES SQ_BUSY_CYCLES SQ_WAVE_CYCLES SQ_WAIT_INST_ANY "
+              "SQ_ACTIVE_INST_VMEM GRBM_GUI_ACTIVE",
+}
+SQ_COUNTERS = ["GRBM_GUI_ACTIVE", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_VMEM", "SQ_BUSY_CYCLES", "SQ_INSTS_VALU",
+               "SQ_WAIT_INST_ANY", "SQ_WAVES", "SQ_WAVE_CYCLES"]
+STEP_KERNELS = {  # summary file: (kernel name in the trace, models per dispatch, sources, alg. B/px)
+    "gmm_step_1280x720_k5.txt": ("gmm_step_kernel<8, 5, 5, true, false, 1>", 8,
+                                 ["paper_2002_00250_amd/csrc/gmm_kernels.hip", "paper_2002_00250_amd/csrc/gmm_device.h",
+                                  "paper_2002_00250_amd/csrc/device_common.h",
+                                  "paper_2002_00250_amd/csrc/fgs_internal.h"], gmm_bytes_per_px()),
+    "pbas_step_1280x720_n35.txt": ("pbas_step_kernel<8, 36, true>", 4,
+                                   ["paper_2002_00250_amd/csrc/pbas_kernels.hip",
+                                    "paper_2002_00250_amd/csrc/pbas_device.h",
+                                    "paper_2002_00250_amd/csrc/device_common.h",
+                                    "paper_2002_00250_amd/csrc/fgs_internal.h"], pbas_bytes_per_px()),
+}
+COPY_KERNEL = "copy_kernel"
+COPY_BYTES = 1 << 30   # the probe's bytes read (and written) per dispatch
+
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(directory, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    if not rows:
+        raise FileNotFoundError(f"no *{suffix} under {directory}")
+    return rows
+
+
+def _counter_means(directory: str):
+    """{kernel name: {counter: mean value per dispatch}} from a --pmc pass."""
+    acc = {}
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        k = r["Kernel_Name"]
+        c = r["Counter_Name"]
+        d = acc.setdefault(k, {}).setdefault(c, {})
+        d[r.get("Dispatch_Id", len(d))] = d.get(r.get("Dispatch_Id", len(d)), 0.0) + float(r["Counter_Value"])
+    return {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def _short_kernel_name(name: str) -> str:
+    """'void ns::(anonymous namespace)::k<1, 2>(args)' -> 'k<1, 2>'."""
+    n = name.strip()
+    if n.startswith("void "):
+        n = n[5:]
+    n = n.replace("(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(n):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            n = n[:i]
+            break
+    head = n if "<" not in n else n[:n.find("<")]
+    return n[head.rfind("::") + 2:] if "::" in head else n
+
+
+def _find_kernel(table: dict, name: str):
+    for k in table:
+        if _short_kernel_name(k) == name:
+            return table[k]
+    raise KeyError(f"kernel {name} not in the profile ({sorted(table)[:6]} ...)")
+
+
+def summarize_profiles(directory: str) -> None:
+    """Write profiles/*_1280x720_*.txt and the kernel statistics table from the rocprofv3 CSV
+    output of PROFILE_PASSES (each under directory/<sub>).  HBM bytes: reads from the EA
+    read requests by size (32, 64 and 128 B), writes from WRITE_SIZE; FETCH_SIZE is kept
+    for reference (it counts a 128-byte request as 64 bytes on this device: the copy
+    kernel's read of 1 GiB reads as half of that)."""
+    import hashlib
+    stats = {r["Name"]: r for r in _csv_rows(os.path.join(directory, "stats"), "kernel_stats.csv")}
+    pmc = {sub: _counter_means(os.path.join(directory, sub)) for sub in PROFILE_PASSES
+           if sub != "stats" and (sub != "pmc_sq" or os.path.isdir(os.path.join(directory, sub)))}
+    cmds = [PROFILE_CMD.format(opts=o, sub=s, name="bench" if s == "stats" else "run")
+            for s, o in PROFILE_PASSES.items()]
+    cmd_text = "commands:\n" + "\n".join("  " + c for c in cmds) + \
+        "\n  python3 $REPO/bench.py --summarize-profiles $OUT\n" \
+        "($REPO = the repository root, $OUT = an output directory; each --pmc pass in its own run)\n"
+
+    def req_bytes(kern):
+        c = _find_kernel(pmc["pmc_rdreq"], kern)
+        return (32 * c["TCC_EA0_RDREQ_32B_sum"] + 64 * c["TCC_EA0_RDREQ_64B_sum"]
+                + 128 * c["TCC_EA0_RDREQ_128B_sum"])
+    copy_fetch = _find_kernel(pmc["pmc_FETCH_SIZE"], COPY_KERNEL)["FETCH_SIZE"] * 1024
+    copy_write = _find_kernel(pmc["pmc_WRITE_SIZE"], COPY_KERNEL)["WRITE_SIZE"] * 1024
+    copy_req = req_bytes(COPY_KERNEL)
+    for fname, (kern, models, sources, alg) in STEP_KERNELS.items():
+        h = hashlib.sha256()
+        for src in sources:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        st = _find_kernel(stats, kern)
+        fetch = _find_kernel(pmc["pmc_FETCH_SIZE"], kern)["FETCH_SIZE"] * 1024
+        write = _find_kernel(pmc["pmc_WRITE_SIZE"], kern)["WRITE_SIZE"] * 1024
+        rq = _find_kernel(pmc["pmc_rdreq"], kern)
+        wq = _find_kernel(pmc["pmc_wrreq"], kern)
+        read = req_bytes(kern)
+        npx = models * H * W
+        lines = [
+            f"# {kern} on 1280x720 frames (benchmark workload: one dispatch steps {models} models)", "",
+            f"kernel: {kern}",
+            f"sources: {' '.join(sources)}",
+            f"sources_sha256_16: {h.hexdigest()[:16]}",
+            f"avg_duration_ns: {float(st['AverageNs']):.0f}",
+            f"calls: {st['Calls']}",
+            f"models_per_dispatch: {models}",
+            f"read_requests_per_dispatch: 32B {rq['TCC_EA0_RDREQ_32B_sum']:.0f}, 64B {rq['TCC_EA0_RDREQ_64B_sum']:.0f}, "
+            f"128B {rq['TCC_EA0_RDREQ_128B_sum']:.0f}",
+            f"write_requests_per_dispatch: all {wq['TCC_EA0_WRREQ_sum']:.0f}, 64B {wq['TCC_EA0_WRREQ_64B_sum']:.0f}",
+            f"read_bytes_per_dispatch: {read:.0f}",
+            f"write_bytes_per_dispatch: {write:.0f}",
+            f"fetch_size_bytes_per_dispatch: {fetch:.0f}",
+            f"hbm_bytes_per_dispatch: {read + write:.0f}",
+            f"hbm_bytes_per_pixel: {(read + write) / npx:.1f}",
+            f"read_bytes_per_pixel: {read / npx:.1f}",
+            f"write_bytes_per_pixel: {write / npx:.1f}",
+            f"algorithmic_bytes_per_pixel: {alg}",
+            f"hbm_GBs_at_avg_duration: {(read + write) / float(st['AverageNs']):.1f}",
+            "",
+            f"Calibration on the plain copy kernel of the same runs ({COPY_KERNEL}, {COPY_BYTES >> 20} MiB read and "
+            f"written per dispatch): read requests {copy_req / COPY_BYTES:.4f} x the bytes read, WRITE_SIZE "
+            f"{copy_write / COPY_BYTES:.4f} x the bytes written, FETCH_SIZE {copy_fetch / COPY_BYTES:.4f} x the "
+            f"bytes read.",
+            "",
+            cmd_text,
+        ]
+        with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
+            fh.write("\n".join(lines))
+    if "pmc_sq" in pmc:
+        sq = ["# SQ counters of the benchmark command's step kernels (1280x720, GMM K=5 + PBAS N=35)", "",
+              "command: " + [c for c in cmds if "SQ_" in c][0],
+              "($REPO = the repository root, $OUT = an output directory)", "",
+              "Averages per dispatch.  GRBM_GUI_ACTIVE is summed over the 8 XCDs (it reads about 8x the",
+              "dispatch's cycles), so the per-XCD busy cycles are GRBM_GUI_ACTIVE / 8.  A wave64 VALU",
+              "instruction occupies its SIMD for 4 cycles.  Derived:",
+              "  VALU busy = SQ_ACTIVE_INST_VALU * 4 / 1024 SIMDs / (GRBM_GUI_ACTIVE / 8)",
+              "  waiting   = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES (share of wave time spent waiting on",
+              "              outstanding memory and other dependencies; same units, unit-free)",
+              "  VALU instructions per wavefront = SQ_INSTS_VALU / SQ_WAVES"]
+        for fname, (kern, models, sources, alg) in STEP_KERNELS.items():
+            h = hashlib.sha256()
+            for src in sources:
+                h.update(open(os.path.join(ROOT, src), "rb").read())
+            c = _find_kernel(pmc["pmc_sq"], kern)
+            busy = c["SQ_ACTIVE_INST_VALU"] * 4 / 1024 / (c["GRBM_GUI_ACTIVE"] / 8)
+            sq += ["", f"kernel: {kern}", f"sources_sha256_16: {h.hexdigest()[:16]}"]
+            sq += [f"  {k}: {c[k]:.0f}" for k in SQ_COUNTERS if k in c]
+            sq += [f"  VALU busy: {100 * busy:.1f} %",
+                   f"  waiting: {100 * c['SQ_WAIT_INST_ANY'] / c['SQ_WAVE_CYCLES']:.1f} %",
+                   f"  VALU instructions per wavefront: {c['SQ_INSTS_VALU'] / c['SQ_WAVES']:.0f}"]
+        with open(os.path.join(ROOT, "profiles", "sq_counters_1280x720_bench.txt"), "w") as fh:
+            fh.write("\n".join(sq) + "\n")
+    tot = sum(float(r["TotalDurationNs"]) for r in stats.values())
+    rows = sorted(stats.values(), key=lambda r: -float(r["TotalDurationNs"]))
+    md = ["# rocprofv3 kernel statistics of the benchmark command (1280x720, GMM K=5 + PBAS N=35)", "",
+          "command: " + cmds[0], "($REPO = the repository root, $OUT = an output directory)", "",
+          "| kernel | calls | avg ns | min ns | max ns | % time |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        md.append(f"| {_short_kernel_name(r['Name'])} | {r['Calls']} | {float(r['AverageNs']):.0f} | {float(r['MinNs']):.0f} | "
+                  f"{float(r['MaxNs']):.0f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
+    with open(os.path.join(ROOT, "profiles", "bench_1280x720_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profiles":
+        summarize_profiles(sys.argv[2])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)

@@ -1,9 +1,10 @@
 """Build libfgs.so for gfx950 with hipcc (in-tree, no JIT cache).
 
     python -m paper_2002_00250_amd.build          # compile every source, link the library
-    python -m paper_2002_00250_amd.build --resource-usage   # the compiler's register,
+    python -m paper_2002_00250_amd.build --resource-usage [FILE]   # the compiler's register,
                                                   # LDS, scratch and occupancy report of the
-                                                  # step, serving and evaluation kernels
+                                                  # step, serving and evaluation kernels (with
+                                                  # FILE: written there as a summary)
 
 Every HIP source is compiled with -ffp-contract=off (no multiply-add fusion: the
 per-pixel recursions must round each operation separately), default IEEE
@@ -75,7 +76,7 @@ REPORT_KERNELS = [
     ("pbas_kernels.hip", "pbas_step_kernelILi1ELi20ELb0E", "pbas_step_kernel<1,20,cached>"),
     ("serve_kernels.hip", "serve_kernelILi5ELi24ELb0E", "serve_kernel<5,24,cached>"),
     ("serve_kernels.hip", "serve_kernelILi5ELi24ELb1E", "serve_kernel<5,24,NT>"),
-    ("eval_kernels.hip", "eval_count_kernelILb1E", "eval_count_kernel<partials>"),
+    ("eval_kernels.hip", "eval_count_kernel", "eval_count_kernel"),
     ("postfilter_kernels.hip", "median_mask_kernelILi4ELi16E", "median_mask_kernel<4,16>"),
 ]
 FIELDS = ["VGPRs", "AGPRs", "TotalSGPRs", "ScratchSize [bytes/lane]", "Occupancy [waves/SIMD]",
@@ -115,9 +116,38 @@ def resource_usage() -> str:
     return "\n".join(rows)
 
 
+def resource_report() -> str:
+    """resource_usage() as a summary: the sources it covers with their hash, the compiler
+    version and the command."""
+    import hashlib
+    heads = ["device_common.h", "fgs_internal.h", "gmm_device.h", "pbas_device.h", "postfilter.h"]
+    paths = [os.path.join("paper_2002_00250_amd", "csrc", s) for s in sorted({k[0] for k in REPORT_KERNELS}) + heads]
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    ver = subprocess.run([hipcc(), "--version"], capture_output=True, text=True).stdout.splitlines()
+    ver = "; ".join(v.strip() for v in ver if "HIP version" in v or "clang version" in v)
+    return "\n".join([
+        "# Compiler resource usage of the step, serving, evaluation and median kernels (gfx950)", "",
+        "sources: " + " ".join(paths),
+        "sources_sha256_16: " + h.hexdigest()[:16],
+        "compiler: " + ver, "",
+        "The compiler's -Rpass-analysis=kernel-resource-usage remarks, with the library's own flags",
+        "(-O3, -ffp-contract=off, packed-FP32 selection off).  Occupancy is waves per SIMD as the",
+        "compiler bounds it from VGPRs, SGPRs and LDS (the hardware maximum is 8).", "",
+        resource_usage(), "",
+        "command:",
+        "  python -m paper_2002_00250_amd.build --resource-usage profiles/compiler_resources_gfx950.txt", ""])
+
+
 if __name__ == "__main__":
     if "--resource-usage" in sys.argv[1:]:
-        print(resource_usage())
+        rest = [a for a in sys.argv[1:] if a != "--resource-usage"]
+        if rest:
+            with open(rest[0], "w") as fh:
+                fh.write(resource_report())
+        else:
+            print(resource_usage())
     else:
         build()
     sys.exit(0)
