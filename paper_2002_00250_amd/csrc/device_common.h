@@ -33,6 +33,14 @@ struct U32x4 {
     uint32_t v[4];
 };
 
+// a ^ b ^ k in one instruction (the three-input bitwise operation, truth table 0x96); k is
+// wave-uniform (the generator's key words)
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t d;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(d) : "v"(a), "v"(b), "s"(k));
+    return d;
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of the keyed bijection on a
 // 128-bit counter.  Each round forms the two 64-bit products of counter words
 // 0 and 2 with the round multipliers and permutes their halves with words 1
@@ -43,8 +51,9 @@ __device__ __forceinline__ U32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // (round 0's words 1 and 3 are the caller's, often constants: left to the compiler)
+        const uint32_t n0 = r == 0 ? (uint32_t)(p1 >> 32) ^ c1 ^ k0 : xor3_key((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = r == 0 ? (uint32_t)(p0 >> 32) ^ c3 ^ k1 : xor3_key((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;

@@ -300,6 +300,7 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     const u16x2 L_gd = h2(lim[1] | (lim[3] << 16));
     const u16x2 cap = {0x200, 0x200};
     const u16x2 one5 = {15, 15};
+    const u16x2 dep1 = {0, 1};
     u16x2 cnt_rb = {0, 0}, cnt_gd = {0, 0};
     u16x2 dmn_rb = {255, 255}, dmn_gd = {255, 255};
 
@@ -326,8 +327,9 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         sm[k] = (sm[k] & ~bm) | (lastw & bm);
         if (k < NLO || k < N) {
             const uint32_t s = sm[k];
-            const u16x2 s_rb = h2(s & 0x00FF00FFu);
-            const u16x2 s_gd = h2(((s >> 8) & 0x00FF00FFu) - 0x00010000u);
+            // byte permutes: R|B and G|D in 16-bit lanes (depth code - 1, empty -> 0xFFFF)
+            const u16x2 s_rb = h2(__builtin_amdgcn_perm(0u, s, 0x0C020C00u));
+            const u16x2 s_gd = h2(__builtin_amdgcn_perm(0u, s, 0x0C030C01u)) - dep1;
             const u16x2 d_rb = __builtin_elementwise_max(s_rb, I_rb) - __builtin_elementwise_min(s_rb, I_rb);
             const u16x2 d_gd = __builtin_elementwise_max(s_gd, I_gd) - __builtin_elementwise_min(s_gd, I_gd);
             dmn_rb = __builtin_elementwise_min(dmn_rb, d_rb);
