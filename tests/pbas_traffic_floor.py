@@ -20,7 +20,7 @@ image width must be a multiple of gran / 4 pixels.  The counts use the oracle's 
 before and after each frame and its Philox words for the self-update slots
 (``PbasRef.last_draws``, ``last_self``); nothing here touches the GPU path.
 
-    python tests/pbas_traffic_floor.py [--frames 100:106] [--out FILE]
+    python tests/pbas_traffic_floor.py [--frames 100:106] [--every K] [--out FILE]
 
 runs the 1280x720 N = 35 benchmark sequence from frame 0 and prints (or writes) the
 per-pixel-frame averages over the given frames at 64- and 128-byte sectors, and the floor
@@ -48,6 +48,16 @@ def _sectors(touched: np.ndarray, px_per_sector: int) -> int:
     H, W = touched.shape
     assert W % px_per_sector == 0, (W, px_per_sector)
     return int(touched.reshape(H, W // px_per_sector, px_per_sector).any(-1).sum())
+
+
+def _plane_sectors(k, y, x, W: int, H: int, px_per_sector: int) -> int:
+    """Distinct (plane k, row y, sector of x) triples among the given pixel events."""
+    assert W % px_per_sector == 0, (W, px_per_sector)
+    if len(k) == 0:
+        return 0
+    key = (np.asarray(k, np.int64) * H + np.asarray(y, np.int64)) * (W // px_per_sector) + \
+        np.asarray(x, np.int64) // px_per_sector
+    return int(np.unique(key).size)
 
 
 def fire_halo_bytes_per_px(H: int, W: int) -> float:
@@ -79,22 +89,25 @@ def step_traffic(ref: PbasRef, rgb: np.ndarray, depth: np.ndarray, grans=(64, 12
     # slots an update lands in, whether or not the byte changes: the self-updates and the
     # neighbour writes (direction (w1 >> 13) & 7, slot ((w1 & 0x1FFF) * N) >> 13, into a
     # neighbour inside the image, the depth channel only where that neighbour has depth)
-    landed = np.zeros((N, H, W), bool)
     ys, xs, js = np.nonzero(upd)
-    landed[kself[ys, xs, js], ys, xs] = True
+    ks = kself[ys, xs, js]
+    self_evt = (ks, ys, xs)                            # D reads, and self-update landings
     ys, xs, js = np.nonzero(ref.last_nb)
     d = ((w1[ys, xs, js] >> np.uint32(13)) & np.uint32(7)).astype(np.int64)
     k = (((w1[ys, xs, js] & np.uint32(0x1FFF)).astype(np.uint64) * np.uint64(N)) >> np.uint64(13)).astype(np.int64)
     ny, nx = ys + NB_DY[d], xs + NB_DX[d]
     ok = (ny >= 0) & (ny < H) & (nx >= 0) & (nx < W)
     ok[ok] &= (js[ok] < 3) | (np.asarray(depth)[ny[ok], nx[ok]] > 0)
-    landed[k[ok], ny[ok], nx[ok]] = True
-    d_read = [(upd & (kself == k)).any(-1) for k in range(N)]
-    d_chg = (ref.D != D0).any(-1)                          # [N, H, W]
-    s_chg = (ref.samples != S0).any(-1)                    # [N, H, W]
+    nb_evt = (k[ok], ny[ok], nx[ok])
+    land_k = np.concatenate([self_evt[0], nb_evt[0]])
+    land_y = np.concatenate([self_evt[1], nb_evt[1]])
+    land_x = np.concatenate([self_evt[2], nb_evt[2]])
+    d_chg = np.nonzero((ref.D != D0).any(-1))                # (k, y, x) of changed D words
+    s_chg = np.nonzero((ref.samples != S0).any(-1))          # (k, y, x) of changed sample words
     pad = last_in_pad(N)
     nq = (N + 3) // 4
     npx = H * W
+    last_q = N // 4 if pad else None                         # quad holding the previous value
     out = {}
     for g in grans:
         dpx, qpx, spx = g // 4, g // 16, g // 8
@@ -103,18 +116,16 @@ def step_traffic(ref: PbasRef, rgb: np.ndarray, depth: np.ndarray, grans=(64, 12
         r["RTS_read"] = 40.0
         r["input_read"] = 5.0
         r["fire_read"] = fire_halo_bytes_per_px(H, W)
-        r["D_read"] = sum(_sectors(d_read[k], dpx) for k in range(N)) * g / npx
-        sw = st = 0
-        for q in range(nq):
-            dirty = s_chg[4 * q:4 * q + 4].any(0)
-            touched = landed[4 * q:4 * q + 4].any(0)
-            if pad and 4 * q <= N < 4 * q + 4:
-                dirty = touched = np.ones_like(dirty)
-            sw += _sectors(dirty, qpx)
-            st += _sectors(touched, qpx)
-        r["samples_write"] = sw * g / npx + (0.0 if pad else 4.0)
-        landed_bytes = st * g / npx + (0.0 if pad else 4.0)
-        r["D_write"] = sum(_sectors(d_chg[k], dpx) for k in range(N)) * g / npx
+        r["D_read"] = _plane_sectors(*self_evt, W, H, dpx) * g / npx
+
+        def quad_sectors(k, y, x):
+            q = np.asarray(k) // 4
+            keep = q != last_q if pad else np.ones(len(q), bool)
+            n = _plane_sectors(q[keep], np.asarray(y)[keep], np.asarray(x)[keep], W, H, qpx)
+            return n + (H * (W // qpx) if pad else 0)        # the previous-value quad: every sector
+        r["samples_write"] = quad_sectors(*s_chg) * g / npx + (0.0 if pad else 4.0)
+        landed_bytes = quad_sectors(land_k, land_y, land_x) * g / npx + (0.0 if pad else 4.0)
+        r["D_write"] = _plane_sectors(*d_chg, W, H, dpx) * g / npx
         r["R_write"] = _sectors((ref.R != R0).any(-1), qpx) * g / npx
         r["T_write"] = _sectors((ref.T != T0).any(-1), qpx) * g / npx
         r["S_write"] = _sectors((ref.S != Sm0).any(-1), spx) * g / npx
@@ -130,6 +141,7 @@ def step_traffic(ref: PbasRef, rgb: np.ndarray, depth: np.ndarray, grans=(64, 12
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", default="100:106", help="first:end of the counted frames")
+    ap.add_argument("--every", type=int, default=1, help="count every k-th frame of the range")
     ap.add_argument("--N", type=int, default=35)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
@@ -144,18 +156,24 @@ def main(argv=None) -> int:
         ref.step(rgb, D)
     acc = {}
     rates = {"self_update": 0.0, "neighbour": 0.0, "foreground": 0.0}
+    counted = list(range(f0, f1, a.every))
+    n = len(counted)
     for t in range(f0, f1):
         rgb, D, _ = sc.frame(t)
+        if t not in counted:
+            ref.step(rgb, D)
+            continue
         res = step_traffic(ref, rgb, D)
         for g, r in res.items():
             for k, v in r.items():
                 acc.setdefault(g, {}).setdefault(k, 0.0)
-                acc[g][k] += v / (f1 - f0)
-        rates["self_update"] += ref.last_self.mean() / (f1 - f0)
-        rates["neighbour"] += ref.last_nb.mean() / (f1 - f0)
-        rates["foreground"] += ref.last_F.any(-1).mean() / (f1 - f0)
+                acc[g][k] += v / n
+        rates["self_update"] += ref.last_self.mean() / n
+        rates["neighbour"] += ref.last_nb.mean() / n
+        rates["foreground"] += ref.last_F.any(-1).mean() / n
     lines = [f"# PBAS N={a.N} traffic floor on the 1280x720 benchmark sequence (oracle count)", "",
-             f"frames: {f0}..{f1 - 1} (model run from frame 0)",
+             f"frames: {f0}..{f1 - 1}" + (f", every {a.every}th counted ({n} frames)" if a.every > 1 else "")
+             + " (model run from frame 0)",
              f"rates per pixel-channel: self-update {rates['self_update']:.4f}, neighbour "
              f"{rates['neighbour']:.4f}; foreground pixels {rates['foreground']:.4f}"]
     reads = ("samples_read", "RTS_read", "input_read", "fire_read", "D_read")
@@ -176,7 +194,7 @@ def main(argv=None) -> int:
         for k, v in acc[g].items():
             if k not in ("total", "samples_landed"):
                 lines.append(f"  {k:16s} {v:8.2f}")
-    lines += ["", "command:", f"  python tests/pbas_traffic_floor.py --frames {a.frames} --N {a.N}"
+    lines += ["", "command:", f"  python tests/pbas_traffic_floor.py --frames {a.frames} --every {a.every} --N {a.N}"
               + (f" --out {a.out}" if a.out else ""), f"({time.time() - t0:.0f} s on the host)"]
     text = "\n".join(lines) + "\n"
     if a.out:
