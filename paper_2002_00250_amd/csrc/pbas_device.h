@@ -149,7 +149,7 @@ __device__ __forceinline__ void scatter_fired(PbasLds<NMAX>& sh, const FireIn& f
                                               uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const uint32_t fb = f.fb[r];
+        const uint32_t fb = f.fb[r] & 0xFu;  // the high nibble carries R flags (pbas_tile)
         if (fb == 0u) continue;
         const int i = (int)threadIdx.x + r * kBlock;
         const int hx = i % kHaloW, hy = i / kHaloW;
@@ -218,8 +218,12 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     // cost occupancy.
     constexpr bool kPadOK = NMAX - NLO <= 7 && NMAX >= 36;
     const bool in_pad = kPadOK && a.m.last_in_pad;
+    // Frame t-1 left in the high nibble of the pixel's fire byte which channels' R equal
+    // their lower bound exactly (where R sits on a static background); where all four do,
+    // R is known without reading it.  Read first, so that the R read, issued after the
+    // samples, need not wait for anything later.
+    const uint32_t rflags = a.apply_pending ? (uint32_t)a.m.fire[(a.t - 1u) & 1u][p] >> 4 : 0u;
     const float4 Tv = a.m.T[p];
-    const float4 Rv = a.m.R[p];
     const uint2 Sv = a.m.S[p];
     uint32_t lastw = in_pad ? 0u : a.m.last[p];
     const uint8_t* px = a.rgb + (int64_t)y * a.rgb_stride + 3 * x;
@@ -246,6 +250,8 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
             for (int i = 0; i < 4; ++i) sm[4 * q + i] = 0u;
         }
     }
+    const float4 Rv = rflags == 0xFu ? make_float4(a.c.R_lower[0], a.c.R_lower[1], a.c.R_lower[2], a.c.R_lower[3])
+                                     : a.m.R[p];
 
     __builtin_amdgcn_sched_barrier(0);
 
@@ -450,7 +456,10 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         if (Sn.x != Sv.x || Sn.y != Sv.y) a.m.S[p] = Sn;
     }
     if (!in_pad) a.m.last[p] = Iw;
-    a.m.fire[a.t & 1u][p] = (uint8_t)fire;
+    uint32_t rfl = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) rfl |= (__float_as_uint(R[j]) == __float_as_uint(a.c.R_lower[j]) ? 1u : 0u) << j;
+    a.m.fire[a.t & 1u][p] = (uint8_t)(fire | (rfl << 4));
 }
 
 // Frames 0..N-1: sample slot t takes the frame; the mask is empty.

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void pbas_flush_kernel(PbasPlanes m, int H, in
         const int qx = x + nb_dx(d), qy = y + nb_dy(d);
         if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
         const int q = qy * W + qx;
-        const uint32_t fb = fire[q];
+        const uint32_t fb = fire[q] & 0xFu;  // channels that fired (the high nibble: R flags)
         if (fb == 0u) continue;
         const U32x4 w1 = philox4x32_10((uint32_t)q, t_prev, 1u, 0u, k0, k1);
         for (int j = 0; j < 4; ++j) {
