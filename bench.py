@@ -48,8 +48,9 @@ def pbas_static_floor_bytes_per_px(N=N_PBAS, T=2.0, channels=4, gran=64, write_g
     probability u = 1/T, each at a uniform slot among N (the per-channel draws of the
     method).  State layout of the step kernel: sample quads of 16 B per pixel (4 pixels
     per 64-byte sector), D history one 4-byte word per slot and pixel (16 pixels per
-    sector).  Counted: every sample quad, R, T, S, input and the fire bytes with their
-    tile halo read; the D-history sectors holding a self-update's old byte read; the
+    sector).  Counted: every sample quad, T, S, input and the fire bytes with their tile
+    halo read (R stays at its lower bound, which the fire bytes flag, so it is not read);
+    the D-history sectors holding a self-update's old byte read; the
     sample-quad sectors a self-update or an incoming neighbour write lands in written,
     with the quad holding the previous-value slot (N >= 33 not a multiple of 4, else a
     plane of its own); mask and fire bytes written.  Left out, as data-dependent: D, S,
@@ -76,7 +77,8 @@ def pbas_static_floor_bytes_per_px(N=N_PBAS, T=2.0, channels=4, gran=64, write_g
         clean = (1.0 - u + u * z) ** (qpx * channels) * (1.0 - u / 8 + u / 8 * z) ** (8 * qpx * channels)
         s_write += 16.0 * (1.0 - clean)
     tiles_halo = ((64 + 2) * (4 + 2)) / (64 * 4)
-    reads = 16.0 * nq + (0 if pad else 4) + 40.0 + 5.0 + tiles_halo + d_read
+    # R sits on its lower bound: flagged in the fire bytes, not read; T and S read
+    reads = 16.0 * nq + (0 if pad else 4) + 24.0 + 5.0 + tiles_halo + d_read
     writes = s_write + (0 if pad else 4) + 2.0
     return {"total": reads + writes, "D_read": d_read, "samples_write": s_write + (0 if pad else 4),
             "reads": reads, "writes": writes}

@@ -6,10 +6,12 @@ pixel, R and T as float4, S as four uint16, the pixel's previous value in the fi
 padding slot for N >= 33 not a multiple of 4).  DRAM moves whole sectors, so what a frame
 must move is counted here per sector of `gran` bytes:
 
-reads   every sample quad (the classification compares all N slots), R, T, S, the RGB
+reads   every sample quad (the classification compares all N slots), T, S, the RGB
         and depth input, the fire bytes of the tile and its 1-pixel halo (64 x 4 tiles),
-        and each D-history sector holding the old byte of a self-update (Sec. 3.2: the
-        update replaces D_k with d_min, and the running sum S needs the value it drops);
+        R where some channel's R is off its lower bound (the fire byte flags the pixels
+        whose four R values sit on it), and each D-history sector holding the old byte of
+        a self-update (Sec. 3.2: the update replaces D_k with d_min, and the running sum S
+        needs the value it drops);
 writes  each sample-quad sector in which some byte changes, plus the quad holding the
         previous-value slot (rewritten every frame), each D sector with a changed byte,
         each R / T / S sector with a changed value, the mask and the fire bytes.
@@ -82,6 +84,7 @@ def step_traffic(ref: PbasRef, rgb: np.ndarray, depth: np.ndarray, grans=(64, 12
         raise ValueError("count updating frames only (the model is still filling)")
     H, W, N = ref.H, ref.W, ref.p.N
     S0, D0, R0, T0, Sm0 = ref.samples.copy(), ref.D.copy(), ref.R.copy(), ref.T.copy(), ref.S.copy()
+    r_bound = (R0.view(np.uint32) == np.array(ref.p.R_lower, np.float32).view(np.uint32)).all(-1)
     ref.step(rgb, depth)
     w0, w1 = ref.last_draws
     kself = (((w0 & np.uint32(0xFFFF)).astype(np.uint64) * np.uint64(N)) >> np.uint64(16)).astype(np.int64)
@@ -113,7 +116,10 @@ def step_traffic(ref: PbasRef, rgb: np.ndarray, depth: np.ndarray, grans=(64, 12
         dpx, qpx, spx = g // 4, g // 16, g // 8
         r = {}
         r["samples_read"] = 16.0 * nq + (0.0 if pad else 4.0)
-        r["RTS_read"] = 40.0
+        r["TS_read"] = 24.0
+        # R is read only where some channel's R left its lower bound: the pixel's fire byte
+        # carries the flags (R_lower itself stands in for it elsewhere)
+        r["R_read"] = _sectors(~r_bound, qpx) * g / npx
         r["input_read"] = 5.0
         r["fire_read"] = fire_halo_bytes_per_px(H, W)
         r["D_read"] = _plane_sectors(*self_evt, W, H, dpx) * g / npx
@@ -176,7 +182,7 @@ def main(argv=None) -> int:
              + " (model run from frame 0)",
              f"rates per pixel-channel: self-update {rates['self_update']:.4f}, neighbour "
              f"{rates['neighbour']:.4f}; foreground pixels {rates['foreground']:.4f}"]
-    reads = ("samples_read", "RTS_read", "input_read", "fire_read", "D_read")
+    reads = ("samples_read", "TS_read", "R_read", "input_read", "fire_read", "D_read")
     for g in sorted(acc):
         lines.append(f"floor_bytes_per_px_{g}: {acc[g]['total']:.1f}")
     # the device's request sizes: every read request a 128-byte line, writes 64-byte sectors
