@@ -614,6 +614,7 @@ STEP_KERNELS = {  # summary file: (kernel name in the trace, models per dispatch
                                     "paper_2002_00250_amd/csrc/fgs_internal.h"], pbas_bytes_per_px()),
 }
 COPY_KERNEL = "copy_kernel"
+PROFILE_STEPS = 200    # the --steps of the profile command: each step kernel's last dispatches
 COPY_BYTES = 1 << 30   # the probe's bytes read (and written) per dispatch
 
 
@@ -629,15 +630,38 @@ def _csv_rows(directory: str, suffix: str):
     return rows
 
 
-def _counter_means(directory: str):
-    """{kernel name: {counter: mean value per dispatch}} from a --pmc pass."""
+def _counter_means(directory: str, last: int | None = None):
+    """{kernel name: {counter: mean value per dispatch}} from a --pmc pass; with `last`,
+    over each kernel's last `last` dispatches only (those of the timed steps)."""
     acc = {}
     for r in _csv_rows(directory, "counter_collection.csv"):
         k = r["Kernel_Name"]
         c = r["Counter_Name"]
         d = acc.setdefault(k, {}).setdefault(c, {})
-        d[r.get("Dispatch_Id", len(d))] = d.get(r.get("Dispatch_Id", len(d)), 0.0) + float(r["Counter_Value"])
-    return {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+        i = int(r["Dispatch_Id"])
+        d[i] = d.get(i, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for k, cs in acc.items():
+        out[k] = {}
+        for c, v in cs.items():
+            vals = [v[i] for i in sorted(v)][-last:] if last else list(v.values())
+            out[k][c] = sum(vals) / len(vals)
+    return out
+
+
+def _trace_durations(directory: str, last: int | None = None):
+    """{kernel name: (mean duration in ns, dispatches)} from a kernel trace; with `last`, over
+    each kernel's last `last` dispatches."""
+    per = {}
+    for r in _csv_rows(directory, "kernel_trace.csv"):
+        per.setdefault(r["Kernel_Name"], []).append(
+            (int(r["Dispatch_Id"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for k, v in per.items():
+        v = [d for _, d in sorted(v)]
+        v = v[-last:] if last else v
+        out[k] = (sum(v) / len(v), len(v))
+    return out
 
 
 def _short_kernel_name(name: str) -> str:
@@ -674,7 +698,8 @@ def summarize_profiles(directory: str) -> None:
     kernel's read of 1 GiB reads as half of that)."""
     import hashlib
     stats = {r["Name"]: r for r in _csv_rows(os.path.join(directory, "stats"), "kernel_stats.csv")}
-    pmc = {sub: _counter_means(os.path.join(directory, sub)) for sub in PROFILE_PASSES
+    timed = _trace_durations(os.path.join(directory, "stats"), PROFILE_STEPS)
+    pmc = {sub: _counter_means(os.path.join(directory, sub), PROFILE_STEPS) for sub in PROFILE_PASSES
            if sub != "stats" and (sub != "pmc_sq" or os.path.isdir(os.path.join(directory, sub)))}
     cmds = [PROFILE_CMD.format(opts=o, sub=s, name="bench" if s == "stats" else "run")
             for s, o in PROFILE_PASSES.items()]
@@ -686,7 +711,7 @@ def summarize_profiles(directory: str) -> None:
         c = _find_kernel(pmc["pmc_rdreq"], kern)
         return (32 * c["TCC_EA0_RDREQ_32B_sum"] + 64 * c["TCC_EA0_RDREQ_64B_sum"]
                 + 128 * c["TCC_EA0_RDREQ_128B_sum"])
-    copy_fetch = _find_kernel(pmc["pmc_FETCH_SIZE"], COPY_KERNEL)["FETCH_SIZE"] * 1024
+    copy_fetch = _find_kernel(pmc["pmc_FETCH_SIZE"], COPY_KERNEL)["FETCH_SIZE"] * 1024  # its 13 dispatches
     copy_write = _find_kernel(pmc["pmc_WRITE_SIZE"], COPY_KERNEL)["WRITE_SIZE"] * 1024
     copy_req = req_bytes(COPY_KERNEL)
     for fname, (kern, models, sources, alg) in STEP_KERNELS.items():
@@ -694,6 +719,7 @@ def summarize_profiles(directory: str) -> None:
         for src in sources:
             h.update(open(os.path.join(ROOT, src), "rb").read())
         st = _find_kernel(stats, kern)
+        avg_ns, n_timed = _find_kernel(timed, kern)
         fetch = _find_kernel(pmc["pmc_FETCH_SIZE"], kern)["FETCH_SIZE"] * 1024
         write = _find_kernel(pmc["pmc_WRITE_SIZE"], kern)["WRITE_SIZE"] * 1024
         rq = _find_kernel(pmc["pmc_rdreq"], kern)
@@ -705,8 +731,10 @@ def summarize_profiles(directory: str) -> None:
             f"kernel: {kern}",
             f"sources: {' '.join(sources)}",
             f"sources_sha256_16: {h.hexdigest()[:16]}",
-            f"avg_duration_ns: {float(st['AverageNs']):.0f}",
+            f"avg_duration_ns: {avg_ns:.0f}",
+            f"timed_dispatches: {n_timed}",
             f"calls: {st['Calls']}",
+            f"avg_duration_all_calls_ns: {float(st['AverageNs']):.0f}",
             f"models_per_dispatch: {models}",
             f"read_requests_per_dispatch: 32B {rq['TCC_EA0_RDREQ_32B_sum']:.0f}, 64B {rq['TCC_EA0_RDREQ_64B_sum']:.0f}, "
             f"128B {rq['TCC_EA0_RDREQ_128B_sum']:.0f}",
@@ -719,7 +747,11 @@ def summarize_profiles(directory: str) -> None:
             f"read_bytes_per_pixel: {read / npx:.1f}",
             f"write_bytes_per_pixel: {write / npx:.1f}",
             f"algorithmic_bytes_per_pixel: {alg}",
-            f"hbm_GBs_at_avg_duration: {(read + write) / float(st['AverageNs']):.1f}",
+            f"hbm_GBs_at_avg_duration: {(read + write) / avg_ns:.1f}",
+            "",
+            f"Durations and counters are averages over the kernel's last {PROFILE_STEPS} dispatches, those of the "
+            f"timed steps (the first ones step the untimed start and warm-up frames); avg_duration_all_calls_ns "
+            f"covers every dispatch.",
             "",
             f"Calibration on the plain copy kernel of the same runs ({COPY_KERNEL}, {COPY_BYTES >> 20} MiB read and "
             f"written per dispatch): read requests {copy_req / COPY_BYTES:.4f} x the bytes read, WRITE_SIZE "
@@ -754,15 +786,30 @@ def summarize_profiles(directory: str) -> None:
                    f"  VALU instructions per wavefront: {c['SQ_INSTS_VALU'] / c['SQ_WAVES']:.0f}"]
         with open(os.path.join(ROOT, "profiles", "sq_counters_1280x720_bench.txt"), "w") as fh:
             fh.write("\n".join(sq) + "\n")
+    _write_stats_table(stats, "bench_1280x720_kernel_stats.md",
+                       "rocprofv3 kernel statistics of the benchmark command (1280x720, GMM K=5 + PBAS N=35)",
+                       cmds[0])
+    short = os.path.join(directory, "stats_short")
+    if os.path.isdir(short):
+        _write_stats_table({r["Name"]: r for r in _csv_rows(short, "kernel_stats.csv")},
+                           "bench_1280x720_short_run_kernel_stats.md",
+                           "rocprofv3 kernel statistics of the default benchmark line at 20 steps (1280x720, "
+                           "GMM K=5 + PBAS N=35, serving and the CPU baseline included)", SHORT_CMD)
+
+
+SHORT_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats --output-format csv -d $OUT/stats_short "
+             "-o bench -- python3 $REPO/bench.py --steps 20 --warmup 5")
+
+
+def _write_stats_table(stats: dict, fname: str, title: str, cmd: str) -> None:
     tot = sum(float(r["TotalDurationNs"]) for r in stats.values())
     rows = sorted(stats.values(), key=lambda r: -float(r["TotalDurationNs"]))
-    md = ["# rocprofv3 kernel statistics of the benchmark command (1280x720, GMM K=5 + PBAS N=35)", "",
-          "command: " + cmds[0], "($REPO = the repository root, $OUT = an output directory)", "",
+    md = ["# " + title, "", "command: " + cmd, "($REPO = the repository root, $OUT = an output directory)", "",
           "| kernel | calls | avg ns | min ns | max ns | % time |", "|---|---|---|---|---|---|"]
     for r in rows:
         md.append(f"| {_short_kernel_name(r['Name'])} | {r['Calls']} | {float(r['AverageNs']):.0f} | {float(r['MinNs']):.0f} | "
                   f"{float(r['MaxNs']):.0f} | {100 * float(r['TotalDurationNs']) / tot:.2f} |")
-    with open(os.path.join(ROOT, "profiles", "bench_1280x720_kernel_stats.md"), "w") as fh:
+    with open(os.path.join(ROOT, "profiles", fname), "w") as fh:
         fh.write("\n".join(md) + "\n")
 
 
