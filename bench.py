@@ -813,6 +813,41 @@ def _write_stats_table(stats: dict, fname: str, title: str, cmd: str) -> None:
         fh.write("\n".join(md) + "\n")
 
 
+MIX_MODES = [  # fgs_mix_probe modes: (mode, planes read, planes written back in place)
+    (0, 10, 10), (1, 10, 5), (2, 10, 0), (3, 0, 10), (4, 9, 9)]
+
+
+def mix_probe_main(args):
+    """What HBM gives the step kernels' access shape without their arithmetic: float4 planes of
+    8 x 1280x720 pixels (1.18 GB for 10 planes), one lane per pixel, non-temporal, read and
+    written back in place in the mixes of MIX_MODES, beside the plain copy."""
+    import torch
+    from paper_2002_00250_amd import fgs
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(dev)
+    npix = 8 * H * W
+    buf = torch.zeros(10 * npix * 16, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    out = {"metric": "HBM GB/s of read/write mixes in the step kernels' access shape", "unit": "GB/s",
+           "n_gpus": 1, "npix": npix, "modes": []}
+    for mode, rp, wp in MIX_MODES:
+        for _ in range(3):
+            fgs.fgs_mix_probe(buf.data_ptr(), npix, mode, stream.cuda_stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        reps = 20
+        for _ in range(reps):
+            fgs.fgs_mix_probe(buf.data_ptr(), npix, mode, stream.cuda_stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        byts = (rp + wp) * 16 * npix
+        out["modes"].append({"mode": mode, "planes_read": rp, "planes_written": wp, "bytes_per_px": (rp + wp) * 16,
+                             "us": round(ms * 1e3, 1), "GBs": round(byts / (ms * 1e-3) / 1e9, 1)})
+    del buf
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profiles":
         summarize_profiles(sys.argv[2])
@@ -842,6 +877,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true", help="time the GMM adjoint window step instead")
     ap.add_argument("--table1", action="store_true", help="time the paper's Table 1 resolutions instead")
     ap.add_argument("--eval", action="store_true", help="time the evaluation counters instead")
+    ap.add_argument("--mix-probe", action="store_true",
+                    help="time the read/write mixes of the step kernels' access shape (fgs_mix_probe) instead")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -867,6 +904,9 @@ def main():
         return
     if args.eval:
         eval_main(args)
+        return
+    if args.mix_probe:
+        mix_probe_main(args)
         return
 
     # A dedicated stream (the legacy null stream has handle 0, which the library reads as

@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define FGS_ABI_VERSION 5
+#define FGS_ABI_VERSION 6
 
 typedef enum fgs_status {
     FGS_OK = 0,
@@ -553,10 +553,19 @@ fgs_status fgs_server_destroy(fgs_server* s);
  *   runs on hip_stream (NULL = default stream) and returns after enqueueing.
  * fgs_copy_probe: a plain streaming device copy of `bytes` (multiple of 16,
  *   both pointers 16-byte aligned) used to calibrate achievable HBM bandwidth.
+ * fgs_mix_probe: the step kernels' access shape without their arithmetic, to
+ *   calibrate what HBM gives a read/write mix: one lane per pixel over float4
+ *   planes of npix pixels at `planes` (device, 16-byte aligned, at least 10 planes,
+ *   i.e. 160*npix bytes, which it overwrites), non-temporal accesses.  mode 0: read
+ *   10 planes, write all 10 back in place; 1: read 10, write the first 5 back
+ *   (about GMM K=5's mix); 2: read 10 only; 3: write 10 only; 4: read 9, write 9
+ *   back (PBAS N=35's sample quads).  Runs on hip_stream, returns after enqueueing.
+ *   INVALID_ARG for a bad buffer, npix or mode.
  */
 fgs_status fgs_philox4x32_10(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                              void* hip_stream);
 fgs_status fgs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
+fgs_status fgs_mix_probe(void* planes, int64_t npix, int32_t mode, void* hip_stream);
 
 #ifdef __cplusplus
 }

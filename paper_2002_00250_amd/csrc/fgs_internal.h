@@ -252,5 +252,6 @@ hipError_t static_launch_clear(uint16_t* count, uint8_t* out, int64_t npix, hipS
 hipError_t diag_launch_philox(uint64_t seed, const uint32_t* ctr, uint32_t* out, int64_t n,
                               hipStream_t s);
 hipError_t diag_launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+hipError_t diag_launch_mix(void* planes, int64_t npix, int mode, hipStream_t s);
 
 }  // namespace fgs

@@ -1282,4 +1282,13 @@ fgs_status fgs_copy_probe(const void* src, void* dst, size_t bytes, void* hip_st
     return FGS_OK;
 }
 
+fgs_status fgs_mix_probe(void* planes, int64_t npix, int32_t mode, void* hip_stream) {
+    if (!planes || npix <= 0 || ((uintptr_t)planes & 15))
+        return fail(FGS_ERR_INVALID_ARG, "mix probe needs a 16-byte aligned buffer and npix > 0");
+    if (mode < 0 || mode > 4) return fail(FGS_ERR_INVALID_ARG, "mix probe mode %d outside 0..4", (int)mode);
+    hipError_t e = diag_launch_mix(planes, npix, mode, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(FGS_ERR_DEVICE, "mix probe kernel: %s", hipGetErrorString(e));
+    return FGS_OK;
+}
+
 }  // extern "C"

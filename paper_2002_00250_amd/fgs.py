@@ -31,7 +31,7 @@ FGS_CACHE_AUTO = 0
 FGS_CACHE_KEEP = 1
 FGS_CACHE_STREAM = 2
 STATE_HEADER_BYTES = 64
-ABI_VERSION = 5          # FGS_ABI_VERSION of include/fgs.h this binding is written against
+ABI_VERSION = 6          # FGS_ABI_VERSION of include/fgs.h this binding is written against
 
 
 class FgsError(RuntimeError):
@@ -129,6 +129,7 @@ def _load():
         "fgs_server_destroy": (S, [c_void_p]),
         "fgs_philox4x32_10": (S, [c_uint64, c_void_p, c_void_p, c_int64, c_void_p]),
         "fgs_copy_probe": (S, [c_void_p, c_void_p, c_size_t, c_void_p]),
+        "fgs_mix_probe": (S, [c_void_p, c_int64, c_int32, c_void_p]),
         "fgs_mask_median": (S, [c_void_p, c_int64, c_void_p, c_int64, c_int32, c_int32, c_int32, c_void_p]),
         "fgs_static_enable": (S, [c_void_p, c_int32]),
         "fgs_static_mask": (S, [c_void_p, c_void_p, c_int64, c_int32]),
@@ -394,6 +395,10 @@ def fgs_philox4x32_10(seed: int, ctr: int, out: int, n: int, hip_stream: int | N
 
 def fgs_copy_probe(src: int, dst: int, nbytes: int, hip_stream: int | None = None) -> None:
     _check(_load().fgs_copy_probe(c_void_p(src), c_void_p(dst), nbytes, c_void_p(hip_stream or 0)))
+
+
+def fgs_mix_probe(planes: int, npix: int, mode: int, hip_stream: int | None = None) -> None:
+    _check(_load().fgs_mix_probe(c_void_p(planes), npix, mode, c_void_p(hip_stream or 0)))
 
 
 def fgs_mask_median(src: int, src_stride: int, dst: int, dst_stride: int, H: int, W: int, radius: int,
