@@ -17,6 +17,11 @@ namespace fgs {
 // over many independent models has one ramp-up and one drain instead of one each.
 constexpr int kBatchMax = 8;
 
+// The PBAS step's tile: a 256-lane workgroup covers kPbasTileW x kPbasTileH pixels, one
+// pixel per lane (the host sizes grids and serving descriptors with the same shape).
+constexpr int kPbasTileW = 64;
+constexpr int kPbasTileH = 4;
+
 // ---------------------------------------------------------------- GMM ----
 // Device layout: per pixel, Kc "core" float4 planes (mu_r, mu_g, mu_b, v) of the
 // colour Gaussians by rank, then E "extra" float4 planes holding, in order, the

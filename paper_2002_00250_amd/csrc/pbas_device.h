@@ -25,8 +25,8 @@
 namespace fgs {
 namespace pbas {
 
-constexpr int kTileW = 64;
-constexpr int kTileH = 4;
+constexpr int kTileW = kPbasTileW;
+constexpr int kTileH = kPbasTileH;
 constexpr int kBlock = kTileW * kTileH;
 constexpr int kHaloW = kTileW + 2;
 constexpr int kHaloH = kTileH + 2;

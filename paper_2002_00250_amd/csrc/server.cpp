@@ -261,8 +261,8 @@ hipError_t issue(fgs_server* s, Batch* b) {
             en.algo = FGS_PBAS;
             en.fill = fill;
             en.p = pa;
-            en.tiles_x = (st->W + 63) / 64;
-            en.ntiles = fill ? (st->npix + 255) / 256 : en.tiles_x * ((st->H + 3) / 4);
+            en.tiles_x = (st->W + kPbasTileW - 1) / kPbasTileW;
+            en.ntiles = fill ? (st->npix + 255) / 256 : en.tiles_x * ((st->H + kPbasTileH - 1) / kPbasTileH);
             streaming = streaming || pa.streaming;
         }
         pre[n] = total;
