@@ -50,7 +50,9 @@ def _both_ways(fgs, m):
 
 @pytest.mark.parametrize("algo,big,small,kw", [
     ("pbas", (120, 200), (37, 70), dict(N=20)),
+    ("pbas", (96, 160), (29, 51), dict(N=12, gradient=1)),   # the gradient variant's export
     ("gmm", (150, 256), (33, 45), dict(Kc=5, Kd=5)),
+    ("gmm", (64, 100), (20, 30), dict(Kc=7, Kd=3, var_mode=1)),
 ])
 def test_noalloc_copy_equals_copy_twice_shrinking(algo, big, small, kw):
     from paper_2002_00250_amd import fgs
