@@ -692,10 +692,10 @@ def _find_kernel(table: dict, name: str):
 
 def summarize_profiles(directory: str) -> None:
     """Write profiles/*_1280x720_*.txt and the kernel statistics table from the rocprofv3 CSV
-    output of PROFILE_PASSES (each under directory/<sub>).  HBM bytes: reads from the EA
-    read requests by size (32, 64 and 128 B), writes from WRITE_SIZE; FETCH_SIZE is kept
-    for reference (it counts a 128-byte request as 64 bytes on this device: the copy
-    kernel's read of 1 GiB reads as half of that)."""
+    output of PROFILE_PASSES (each under directory/<sub>).  HBM bytes: FETCH_SIZE and
+    WRITE_SIZE, each divided by what the counter reads for the plain copy kernel of the same
+    runs (FETCH_SIZE counts a 128-byte read request as 64 bytes on this device); the read
+    requests by size (32, 64 and 128 B) cross-check the reads."""
     import hashlib
     stats = {r["Name"]: r for r in _csv_rows(os.path.join(directory, "stats"), "kernel_stats.csv")}
     timed = _trace_durations(os.path.join(directory, "stats"), PROFILE_STEPS)
@@ -724,7 +724,12 @@ def summarize_profiles(directory: str) -> None:
         write = _find_kernel(pmc["pmc_WRITE_SIZE"], kern)["WRITE_SIZE"] * 1024
         rq = _find_kernel(pmc["pmc_rdreq"], kern)
         wq = _find_kernel(pmc["pmc_wrreq"], kern)
-        read = req_bytes(kern)
+        req_read = req_bytes(kern)
+        # HBM bytes: each counter divided by what it reads for the copy of known size
+        fetch_scale = copy_fetch / COPY_BYTES
+        write_scale = copy_write / COPY_BYTES
+        read = fetch / fetch_scale
+        write = write / write_scale
         npx = models * H * W
         lines = [
             f"# {kern} on 1280x720 frames (benchmark workload: one dispatch steps {models} models)", "",
@@ -739,9 +744,13 @@ def summarize_profiles(directory: str) -> None:
             f"read_requests_per_dispatch: 32B {rq['TCC_EA0_RDREQ_32B_sum']:.0f}, 64B {rq['TCC_EA0_RDREQ_64B_sum']:.0f}, "
             f"128B {rq['TCC_EA0_RDREQ_128B_sum']:.0f}",
             f"write_requests_per_dispatch: all {wq['TCC_EA0_WRREQ_sum']:.0f}, 64B {wq['TCC_EA0_WRREQ_64B_sum']:.0f}",
+            f"fetch_size_kib_per_dispatch: {fetch / 1024:.0f}",
+            f"write_size_kib_per_dispatch: {_find_kernel(pmc['pmc_WRITE_SIZE'], kern)['WRITE_SIZE']:.0f}",
+            f"fetch_scale: {fetch_scale:.4f}",
+            f"write_scale: {write_scale:.4f}",
             f"read_bytes_per_dispatch: {read:.0f}",
             f"write_bytes_per_dispatch: {write:.0f}",
-            f"fetch_size_bytes_per_dispatch: {fetch:.0f}",
+            f"read_bytes_from_request_sizes: {req_read:.0f}",
             f"hbm_bytes_per_dispatch: {read + write:.0f}",
             f"hbm_bytes_per_pixel: {(read + write) / npx:.1f}",
             f"read_bytes_per_pixel: {read / npx:.1f}",
@@ -753,10 +762,12 @@ def summarize_profiles(directory: str) -> None:
             f"timed steps (the first ones step the untimed start and warm-up frames); avg_duration_all_calls_ns "
             f"covers every dispatch.",
             "",
-            f"Calibration on the plain copy kernel of the same runs ({COPY_KERNEL}, {COPY_BYTES >> 20} MiB read and "
-            f"written per dispatch): read requests {copy_req / COPY_BYTES:.4f} x the bytes read, WRITE_SIZE "
-            f"{copy_write / COPY_BYTES:.4f} x the bytes written, FETCH_SIZE {copy_fetch / COPY_BYTES:.4f} x the "
-            f"bytes read.",
+            f"HBM bytes = FETCH_SIZE / fetch_scale + WRITE_SIZE / write_scale, the scales being what the counters "
+            f"read on the plain copy kernel of the same runs ({COPY_KERNEL}, {COPY_BYTES >> 20} MiB read and written "
+            f"per dispatch): FETCH_SIZE {copy_fetch / COPY_BYTES:.4f} x the bytes read (it counts a 128-byte read "
+            f"request as 64 bytes), WRITE_SIZE {copy_write / COPY_BYTES:.4f} x the bytes written.  Cross-check: the "
+            f"read requests by size (32, 64, 128 B) give {req_read:.0f} read bytes per dispatch "
+            f"({copy_req / COPY_BYTES:.4f} x the copy's bytes read).",
             "",
             cmd_text,
         ]

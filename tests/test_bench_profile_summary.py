@@ -89,16 +89,20 @@ def test_summary_averages_the_timed_dispatches(profile_dir):
     assert float(kv["avg_duration_ns"]) == pytest.approx((100 + 102 + 104 + 106) / 4)
     assert int(kv["timed_dispatches"]) == 4
     assert float(kv["avg_duration_all_calls_ns"]) == pytest.approx((5 * 900 + 412) / 9, abs=0.5)  # whole ns
-    # reads from the request sizes: 32 + 2 * 64 + 3 * 128 bytes per dispatch (timed ones)
-    assert float(kv["read_bytes_per_dispatch"]) == pytest.approx(32 + 128 + 384)
+    # reads: FETCH_SIZE (1000 B per timed dispatch) over the copy's scale 0.5; writes:
+    # WRITE_SIZE (2048 B) over the copy's scale 1; the request sizes cross-check the reads
+    # (32 + 2 * 64 + 3 * 128 bytes per timed dispatch)
+    assert float(kv["fetch_scale"]) == pytest.approx(0.5) and float(kv["write_scale"]) == pytest.approx(1.0)
+    assert float(kv["read_bytes_per_dispatch"]) == pytest.approx(2000)
     assert float(kv["write_bytes_per_dispatch"]) == pytest.approx(2048)
-    assert float(kv["hbm_bytes_per_dispatch"]) == pytest.approx(544 + 2048)
+    assert float(kv["hbm_bytes_per_dispatch"]) == pytest.approx(2000 + 2048)
+    assert float(kv["read_bytes_from_request_sizes"]) == pytest.approx(32 + 128 + 384)
     kp = bench._kv(str(out / "pbas_step_1280x720_n35.txt"))
     assert float(kp["avg_duration_ns"]) == pytest.approx(200)
     text = (out / "pbas_step_1280x720_n35.txt").read_text()
-    assert "read requests 1.0000 x the bytes read" in text and "FETCH_SIZE 0.5000" in text
+    assert "(1.0000 x the copy's bytes read)" in text and "FETCH_SIZE 0.5000" in text
     # bench reads the traffic back while the sources' hash matches, and not after a change
-    assert bench.measured_traffic("pbas_step_1280x720_n35.txt") == pytest.approx(544 + 2048)
+    assert bench.measured_traffic("pbas_step_1280x720_n35.txt") == pytest.approx(2000 + 2048)
     src = os.path.join(bench.ROOT, bench.STEP_KERNELS["pbas_step_1280x720_n35.txt"][2][0])
     with open(src, "a") as fh:
         fh.write(" changed")
