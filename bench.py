@@ -860,9 +860,6 @@ def mix_probe_main(args):
 
 
 def main():
-    if len(sys.argv) == 3 and sys.argv[1] == "--summarize-profiles":
-        summarize_profiles(sys.argv[2])
-        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
@@ -890,7 +887,13 @@ def main():
     ap.add_argument("--eval", action="store_true", help="time the evaluation counters instead")
     ap.add_argument("--mix-probe", action="store_true",
                     help="time the read/write mixes of the step kernels' access shape (fgs_mix_probe) instead")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write the profiles/ summaries from the rocprofv3 output of the profile passes in DIR "
+                         "(no GPU)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(each camera stream is independent: sharding is by stream, one process per GPU)",
