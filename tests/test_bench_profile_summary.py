@@ -103,6 +103,9 @@ def test_summary_averages_the_timed_dispatches(profile_dir):
     assert "(1.0000 x the copy's bytes read)" in text and "FETCH_SIZE 0.5000" in text
     # bench reads the traffic back while the sources' hash matches, and not after a change
     assert bench.measured_traffic("pbas_step_1280x720_n35.txt") == pytest.approx(2000 + 2048)
+    # per model-frame: a PBAS dispatch of the benchmark steps 4 models, a GMM one 8
+    assert bench.measured_traffic_per_model("pbas_step_1280x720_n35.txt") == pytest.approx((2000 + 2048) / 4)
+    assert bench.measured_traffic_per_model("gmm_step_1280x720_k5.txt") == pytest.approx((2000 + 2048) / 8)
     src = os.path.join(bench.ROOT, bench.STEP_KERNELS["pbas_step_1280x720_n35.txt"][2][0])
     with open(src, "a") as fh:
         fh.write(" changed")
