@@ -117,6 +117,51 @@ def test_benchmark_kernel_instances_on_distinct_models():
     _all_equal(_run_batched(specs, 50, seed=120, policy=fgs.FGS_CACHE_STREAM))
 
 
+def test_kinds_on_two_streams_overlapping():
+    # The benchmark's --kind-streams mode: the 8-model GMM launch on one stream and the
+    # 4-model PBAS launch on another, issued back to back with the raw batch call (no
+    # stream waits between them), so the two kinds run at the same time on the device.
+    # Every model still equals its oracle run.
+    from paper_2002_00250_amd import fgs
+    G, P = fgs.FGS_GMM, fgs.FGS_PBAS
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    gsizes = [(37, 129), (48, 80), (1, 257), (64, 64), (33, 70), (20, 300), (45, 131), (17, 95)]
+    psizes = [(21, 70), (45, 131), (9, 130), (64, 66)]
+    specs = [(G, H, W, GmmParams(Kc=5, Kd=5), sa) for H, W in gsizes]
+    specs += [(P, H, W, PbasParams(N=35, seed=200 + k), sb) for k, (H, W) in enumerate(psizes)]
+    frames = 45
+    models, refs, inputs = [], [], []
+    for k, (algo, H, W, p, st) in enumerate(specs):
+        cp = _gmm_params_c(p) if algo == G else _pbas_params_c(p)
+        m = fgs.Model(algo, H, W, cp, stream=st)
+        fgs.fgs_set_cache_policy(m.handle, fgs.FGS_CACHE_STREAM)
+        models.append(m)
+        refs.append(GmmRef(H, W, p) if algo == G else PbasRef(H, W, p))
+        sc = Scene(preset("pbas_640x480", H=H, W=W, seed=300 + k))
+        inputs.append([sc.frame(t)[:2] for t in range(frames)])
+    dev = [[to_dev(rgb, D) for rgb, D in fr] for fr in inputs]
+    torch.cuda.synchronize()      # every frame resident before the first launch
+    kinds = [[k for k, sp in enumerate(specs) if sp[0] == a] for a in (G, P)]
+    diff = [0] * len(specs)
+    for t in range(frames):
+        for ks in kinds:
+            fgs.fgs_push_frames([models[k].handle for k in ks], [dev[k][t][0].data_ptr() for k in ks],
+                                [dev[k][t][0].stride(0) for k in ks], [dev[k][t][1].data_ptr() for k in ks],
+                                [2 * dev[k][t][1].stride(0) for k in ks])
+        for k, (m, ref) in enumerate(zip(models, refs)):
+            e = ref.step(*inputs[k][t])
+            diff[k] += int((m.mask_host() != e).sum())
+    res = []
+    for (algo, H, W, _, _), m, ref, dk in zip(specs, models, refs, diff):
+        if algo == G:
+            n, bad, neq = compare_gmm_state(m.state(), ref.state_planes())
+            res.append(("gmm", H, W, dk, {"bad": bad, "not_bit_equal": neq}))
+        else:
+            res.append(("pbas", H, W, dk, compare_pbas_state(m.state(), ref.state_planes())))
+        m.close()
+    _all_equal(res)
+
+
 def test_argument_checks_leave_models_untouched():
     from paper_2002_00250_amd import fgs
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
