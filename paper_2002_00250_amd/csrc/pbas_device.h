@@ -316,13 +316,11 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     const uint32_t keep = (lastw >> 24) != 0u ? 0xFFFFFFFFu : 0x00FFFFFFu;  // depth at t-1?
 #pragma unroll
     for (int w = 0; w < NW; ++w) pw[w] = a.apply_pending ? sh.pend[w * kBlock + tid] & keep : 0u;
-    // Quad q of the samples can change only where a pending or self-update bit of one
-    // of its slots is set (nibble q & 1 of every byte of bit-word q >> 1) or where it
-    // holds the previous-value slot; bit q of `dirty`.
-    uint32_t dirty = 0u;
-#pragma unroll
-    for (int q = 0; q < NMAX / 4; ++q)
-        dirty |= ((pw[q >> 1] & ((q & 1) ? 0xF0F0F0F0u : 0x0F0F0F0Fu)) != 0u ? 1u : 0u) << q;
+    // Bit q of `dirty`: some byte of sample quad q changed, by the neighbour writes
+    // merged here (each merged slot compared with the word it replaces, four slots to a
+    // quad; the empty asm keeps each quad's test next to its slots, where the words are
+    // in registers anyway), then by the previous value and the self-update below.
+    uint32_t dirty = 0u, chg = 0u;
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         // Keep the per-slot work next to its sample: without the fence the scheduler
@@ -330,7 +328,14 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         // registers.
         if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
         const uint32_t bm = slot_byte_mask(pw[k >> 3], k);
-        sm[k] = (sm[k] & ~bm) | (lastw & bm);
+        const uint32_t before = sm[k];
+        sm[k] = (before & ~bm) | (lastw & bm);
+        chg |= sm[k] ^ before;
+        if ((k & 3) == 3) {
+            dirty |= (chg != 0u ? 1u : 0u) << (k >> 2);
+            chg = 0u;
+            asm volatile("" : "+v"(dirty));
+        }
         if (k < NLO || k < N) {
             const uint32_t s = sm[k];
             // byte permutes: R|B and G|D in 16-bit lanes (depth code - 1, empty -> 0xFFFF)
@@ -358,27 +363,6 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     }
     a.m.mask[p] = fg ? (uint8_t)255 : (uint8_t)0;
 
-    // Self-update: sample slot ks[j] takes I_j (byte masks from bit-words built
-    // in registers), its D slot takes d_min.
-    {
-        uint32_t sw[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-            uint32_t v = 0u;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                v |= (upd[j] && (ks[j] >> 3) == w) ? 1u << (8 * j + (ks[j] & 7)) : 0u;
-            sw[w] = v;
-        }
-#pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            const uint32_t bm = slot_byte_mask(sw[k >> 3], k);
-            sm[k] = (sm[k] & ~bm) | (Iw & bm);
-        }
-#pragma unroll
-        for (int q = 0; q < NMAX / 4; ++q)
-            dirty |= ((sw[q >> 1] & ((q & 1) ? 0xF0F0F0F0u : 0x0F0F0F0Fu)) != 0u ? 1u : 0u) << q;
-    }
     // A D-history byte is written only when it changes: on a static background d_min is
     // mostly 0 or 1 and often equals the byte it replaces, and each write that is left
     // out saves a partial-sector write to HBM.
@@ -418,33 +402,59 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         T[j] = fminf(fmaxf(tt, a.c.T_lower), a.c.T_upper);
     }
 
-    // The store loop rebuilds each quad plane's descriptor (a few scalar
-    // instructions) rather than keeping them alive across the frame; the empty asm
-    // hides that the base is the one the loads used.
+    // Self-update: sample slot ks[j] takes I_j (byte masks from bit-words built in
+    // registers), merged quad by quad right before the quad's store, so that each quad's
+    // words die at its store.  A 64-byte sector of a quad plane holds 4 consecutive
+    // pixels (lanes 4i..4i+3 of a tile row): a quad's store is left out only where no
+    // byte of it changed in any of the 4, so the writes that remain cover whole sectors.
+    // Lanes past the image edge have left and can only add bits to the vote (a store
+    // too many, never one too few).
+    // (Up to 40 slots: for more, the bits' registers would cost occupancy.)
+    constexpr bool kSkipClean = NMAX <= 40;
+    uint32_t sw[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        uint32_t v = 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            v |= (upd[j] && (ks[j] >> 3) == w) ? 1u << (8 * j + (ks[j] & 7)) : 0u;
+        sw[w] = v;
+    }
     if (in_pad) {
 #pragma unroll
         for (int k = NLO; k < NMAX; ++k)
-            if (k == N) sm[k] = Iw;
-        dirty |= 1u << (N >> 2);
+            if (k == N) {
+                dirty |= (sm[k] != Iw ? 1u : 0u) << (k >> 2);
+                sm[k] = Iw;
+            }
     }
-    // A 64-byte sector of a quad plane holds 4 consecutive pixels (lanes 4i..4i+3 of a
-    // tile row): a quad's store is left out only where it changed in none of the 4, so
-    // every write still covers whole sectors.  Lanes past the image edge have left and
-    // can only add bits (a store too many, never one too few).
-    // (Up to 40 slots: for more, the bits' registers would cost occupancy.)
-    constexpr bool kSkipClean = NMAX <= 40;
-    if (kSkipClean) {
-        dirty |= __shfl_xor(dirty, 1, 64);
-        dirty |= __shfl_xor(dirty, 2, 64);
-    }
+    // The store loop rebuilds each quad plane's descriptor (a few scalar
+    // instructions) rather than keeping them alive across the frame; the empty asm
+    // hides that the base is the one the loads used.
     uint32_t* sbase = a.m.samples + p0 * 4;
     asm volatile("" : "+s"(sbase));
 #pragma unroll
-    for (int q = 0; q < NMAX / 4; ++q)
-        if ((4 * q < NLO || 4 * q < N) && (!kSkipClean || ((dirty >> q) & 1u))) {
+    for (int q = 0; q < NMAX / 4; ++q) {
+        if (!(4 * q < NLO || 4 * q < N)) continue;
+        uint32_t c = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * q + i;
+            const uint32_t bm = slot_byte_mask(sw[k >> 3], k);
+            const uint32_t before = sm[k];
+            sm[k] = (before & ~bm) | (Iw & bm);
+            c |= sm[k] ^ before;
+        }
+        int d = (int)(((dirty >> q) & 1u) | (c != 0u ? 1u : 0u));
+        if (kSkipClean) {  // OR over each group of 4 lanes (quad permutes [1,0,3,2], [2,3,0,1])
+            d |= __builtin_amdgcn_update_dpp(0, d, 0xB1, 0xF, 0xF, false);
+            d |= __builtin_amdgcn_update_dpp(0, d, 0x4E, 0xF, 0xF, false);
+        }
+        if (!kSkipClean || d) {
             const u32x4 v = {sm[4 * q], sm[4 * q + 1], sm[4 * q + 2], sm[4 * q + 3]};
             st_quad<NT>(sbase, npix, qrange, q, voff, v);
         }
+    }
     // R, T and S are written only where they changed (bit for bit): on a static
     // background R and T sit at their lower bounds and S moves only with D.
     {
