@@ -87,7 +87,8 @@ __device__ __forceinline__ void intent_of(uint32_t word, int N, int& dir, int& s
 // of channel j, bit 8*j + (k & 7) of word k >> 3.  Shifting word k >> 3 right by
 // k & 7 and masking with 0x01010101 leaves one bit per channel in the low bit of
 // that channel's byte, which a 16-bit lane multiply by 0xFF widens into a byte
-// mask of the sample word.
+// mask of the sample word (slot_byte_mask, for run-time slot indices); the unrolled
+// slot loops merge with a byte permute instead (merge_slot, one instruction fewer).
 constexpr uint32_t kLowBits = 0x01010101u;
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
@@ -104,6 +105,20 @@ __device__ __forceinline__ bool differs(float4 a, float4 b) {
 __device__ __forceinline__ uint32_t slot_byte_mask(uint32_t word, int k) {
     const uint32_t bits = (word >> (k & 7)) & kLowBits;
     return w32(h2(bits) * (u16x2){0xFF, 0xFF});
+}
+
+// Slot k's sample word with the bytes of `val` in place of those whose channel bit is
+// set for slot k in bit-word `word`, the rest from `cur`: the bits are shifted to bit 2
+// of their channel's byte, which then selects byte j + 4 (val) instead of byte j (cur)
+// in a byte permute.  (k is a constant in the unrolled slot loops, so the shift is one
+// instruction in a fixed direction.)  `byte_ids` holds 0x03020100.
+__device__ __forceinline__ uint32_t merge_slot(uint32_t cur, uint32_t val, uint32_t word, int k,
+                                               uint32_t byte_ids) {
+    const int s = k & 7;
+    const uint32_t x = s >= 2 ? word >> (s - 2) : word << (2 - s);
+    uint32_t sel;  // (x & 0x04040404) | byte_ids in one three-input logic instruction
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xea" : "=v"(sel) : "v"(x), "s"(0x04040404u), "v"(byte_ids));
+    return __builtin_amdgcn_perm(val, cur, sel);
 }
 
 // LDS a tile needs: the pending bit-words, word w of tile pixel i at [w][i].
@@ -321,15 +336,16 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     // quad; the empty asm keeps each quad's test next to its slots, where the words are
     // in registers anyway), then by the previous value and the self-update below.
     uint32_t dirty = 0u, chg = 0u;
+    uint32_t byte_ids;  // an opaque register, so the constant is not rematerialised per merge
+    asm("v_mov_b32 %0, 0x03020100" : "=v"(byte_ids));
 #pragma unroll
     for (int k = 0; k < NMAX; ++k) {
         // Keep the per-slot work next to its sample: without the fence the scheduler
         // runs the mask arithmetic of every slot ahead of the loads and holds N more
         // registers.
         if ((k & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-        const uint32_t bm = slot_byte_mask(pw[k >> 3], k);
         const uint32_t before = sm[k];
-        sm[k] = (before & ~bm) | (lastw & bm);
+        sm[k] = merge_slot(before, lastw, pw[k >> 3], k, byte_ids);
         chg |= sm[k] ^ before;
         if ((k & 3) == 3) {
             dirty |= (chg != 0u ? 1u : 0u) << (k >> 2);
@@ -440,9 +456,8 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = 4 * q + i;
-            const uint32_t bm = slot_byte_mask(sw[k >> 3], k);
             const uint32_t before = sm[k];
-            sm[k] = (before & ~bm) | (Iw & bm);
+            sm[k] = merge_slot(before, Iw, sw[k >> 3], k, byte_ids);
             c |= sm[k] ^ before;
         }
         int d = (int)(((dirty >> q) & 1u) | (c != 0u ? 1u : 0u));
