@@ -187,9 +187,11 @@ __device__ __forceinline__ void scatter_fired(PbasLds<NMAX>& sh, const FireIn& f
 // N lies in [NLO, NMAX]: slots below NLO need no run-time bound check.
 //
 // The pixel's N sample words live in registers between one dense coalesced read
-// and one dense coalesced write of the sample quad planes: frame t-1's neighbour
-// writes and this frame's self-update are merged in registers with per-slot byte
-// masks, so no sample quad plane sees a partial-line write.  Every read of the frame
+// and the write-back of the sample quad planes: frame t-1's neighbour writes and
+// this frame's self-update are merged in registers slot by slot (byte permutes), and
+// a quad goes back to memory, in whole 64-byte sectors, only where a byte of it
+// changed in one of the sector's 4 pixels, so no quad plane sees a partial-sector
+// write.  Every read of the frame
 // is issued before the scatter of the neighbour writes (fire bytes first, then
 // the pixel's state and samples), and since the Philox draws and the 1/T tests
 // do not depend on the classification, the candidate self-update slots are known
@@ -418,8 +420,8 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
         T[j] = fminf(fmaxf(tt, a.c.T_lower), a.c.T_upper);
     }
 
-    // Self-update: sample slot ks[j] takes I_j (byte masks from bit-words built in
-    // registers), merged quad by quad right before the quad's store, so that each quad's
+    // Self-update: sample slot ks[j] takes I_j (from bit-words built in registers,
+    // merged as above), quad by quad right before the quad's store, so that each quad's
     // words die at its store.  A 64-byte sector of a quad plane holds 4 consecutive
     // pixels (lanes 4i..4i+3 of a tile row): a quad's store is left out only where no
     // byte of it changed in any of the 4, so the writes that remain cover whole sectors.
