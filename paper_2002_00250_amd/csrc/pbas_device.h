@@ -429,15 +429,19 @@ __device__ __forceinline__ void pbas_tile(const PbasStepArgs& a, int bx, int by,
     // too many, never one too few).
     // (Up to 40 slots: for more, the bits' registers would cost occupancy.)
     constexpr bool kSkipClean = NMAX <= 40;
+    // The self-update's bit-words are built in the lane's own LDS words (read into pw
+    // before the classification, touched by no other lane since the scatter's barrier):
+    // cleared, then one OR per updating channel, then read back.
     uint32_t sw[NW];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        uint32_t v = 0u;
+    for (int w = 0; w < NW; ++w) sh.pend[w * kBlock + tid] = 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            v |= (upd[j] && (ks[j] >> 3) == w) ? 1u << (8 * j + (ks[j] & 7)) : 0u;
-        sw[w] = v;
-    }
+    for (int j = 0; j < 4; ++j)
+        if (upd[j])
+            __hip_atomic_fetch_or(&sh.pend[(ks[j] >> 3) * kBlock + tid], 1u << (8 * j + (ks[j] & 7)),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sw[w] = sh.pend[w * kBlock + tid];
     if (in_pad) {
 #pragma unroll
         for (int k = NLO; k < NMAX; ++k)
