@@ -33,9 +33,11 @@ constexpr int kHaloH = kTileH + 2;
 
 // 8-neighbourhood indexed by the 3-bit direction field: (dx, dy) =
 // (-1,-1) (0,-1) (1,-1) (-1,0) (1,0) (-1,1) (0,1) (1,1).  The table is point
-// symmetric: the opposite of direction d is 7 - d.
-__device__ __forceinline__ int nb_dx(int d) { return (d == 0 || d == 3 || d == 5) ? -1 : ((d == 1 || d == 6) ? 0 : 1); }
-__device__ __forceinline__ int nb_dy(int d) { return d < 3 ? -1 : (d < 5 ? 0 : 1); }
+// symmetric: the opposite of direction d is 7 - d.  dx + 1 and dy + 1 are packed two
+// bits per direction (bits 2d, 2d + 1), so a lookup is a bit-field extract with no
+// branch: dx + 1 = 0,1,2,0,2,0,1,2 -> 0x9224; dy + 1 = 0,0,0,1,1,2,2,2 -> 0xA940.
+__device__ __forceinline__ int nb_dx(int d) { return (int)((0x9224u >> (2 * d)) & 3u) - 1; }
+__device__ __forceinline__ int nb_dy(int d) { return (int)((0xA940u >> (2 * d)) & 3u) - 1; }
 
 // D history: slot k of pixel p is the 32-bit word k * npix + p (one byte per channel).
 __device__ __forceinline__ uint8_t* byte_at(uint32_t* plane0, int64_t npix, int slot, int p, int j) {
